@@ -1,0 +1,189 @@
+"""Pins of the oracle's mark / resolve / cache simulator (paper: Method,
+Mark, Resolve, Update Cache; Texture Block Cache).
+
+Mark is pinned to resolve by perturbation (a block is marked exactly when
+the unrounded frame depends on its texels), resolve to closed forms (texel
+centres reproduce the texture, half-texel offsets average four texels,
+constant textures give constant frames, uv repeats, trilinear at integer
+lod equals bilinear), the LRU simulator to its invariants and to a
+brute-force oldest-first check."""
+import numpy as np
+import pytest
+from hypothesis import given, settings
+from hypothesis import strategies as st
+
+import oracle
+from paper_2510_08166_amd.synth import GPIXEL_DTYPE, configs, make_textures, EncodedTexture, encode
+
+NEAREST, BILINEAR, TRILINEAR = oracle.NEAREST, oracle.BILINEAR, oracle.TRILINEAR
+
+
+def gb(u, v, tex=0, lod=0.0):
+    u = np.atleast_2d(np.asarray(u, np.float32)); v = np.atleast_2d(np.asarray(v, np.float32))
+    g = np.zeros(u.shape, GPIXEL_DTYPE)
+    g["u"], g["v"], g["tex"], g["lod"] = u, v, tex, lod
+    return g
+
+
+@pytest.fixture(scope="module")
+def small_scene():
+    tex = make_textures([(11, 64, 64, 80, 420, 4), (12, 48, 32, 60, 444, 3)], keep_rgb=True)
+    return oracle.Scene(tex)
+
+
+def test_layout_is_32_aligned(small_scene):
+    s = small_scene
+    assert np.all(s.blk_base % 32 == 0)
+    assert s.n_blocks % 32 == 0
+    ends = s.blk_base + s.blk_cols * s.blk_rows
+    assert np.all(ends[:-1] <= s.blk_base[1:])
+
+
+def test_tiny_marks_every_block_and_reproduces_texture():
+    wl = configs.tiny()
+    s = oracle.Scene(wl.textures)
+    frame, vis, bad = s.render(wl.views[0], NEAREST)
+    assert bad == 0 and len(vis) == 256 and s.n_blocks == 256
+    lvl = s.decode_level(0)
+    assert np.array_equal(oracle.unpack_frame(frame)[:, :, :3], lvl)
+    assert (oracle.unpack_frame(frame)[:, :, 3] == 255).all()
+
+
+def test_bilinear_at_texel_centres_is_nearest(small_scene):
+    s = small_scene
+    x, y = np.meshgrid(np.arange(64), np.arange(64))
+    g = gb((x + 0.5) / 64, (y + 0.5) / 64, tex=0, lod=0.0)
+    lv = {0: s.decode_level(0)}
+    fb, _ = s.resolve(g, BILINEAR, lv)
+    fn, _ = s.resolve(g, NEAREST, lv)
+    assert np.array_equal(fb, fn)
+    assert np.array_equal(oracle.unpack_frame(fn)[:, :, :3], lv[0])
+
+
+def test_bilinear_half_texel_is_rounded_average(small_scene):
+    s = small_scene
+    img = s.decode_level(0).astype(np.int64)
+    x, y = np.meshgrid(np.arange(63), np.arange(63))
+    g = gb((x + 1.0) / 64, (y + 1.0) / 64)          # s = x + 0.5: weights 128/128
+    fb, _ = s.resolve(g, BILINEAR, {0: s.decode_level(0)})
+    want = (img[:-1, :-1] + img[:-1, 1:] + img[1:, :-1] + img[1:, 1:]) * 128 * 128
+    want = (want + 32768) >> 16
+    assert np.array_equal(oracle.unpack_frame(fb)[:, :, :3].astype(np.int64), want)
+
+
+def test_repeat_addressing(small_scene):
+    s = small_scene
+    rng = np.random.default_rng(3)
+    u = rng.random((16, 16)).astype(np.float32); v = rng.random((16, 16)).astype(np.float32)
+    lv = {L: s.decode_level(L) for L in range(len(s.jpegs))}
+    for f in (NEAREST, BILINEAR):
+        a, _ = s.resolve(gb(u, v), f, lv)
+        b, _ = s.resolve(gb(u + 3.0, v - 2.0), f, lv)
+        assert np.array_equal(a, b)
+
+
+def test_constant_texture_constant_frame():
+    rgb = np.zeros((64, 64, 3), np.uint8); rgb[...] = (200, 30, 90)
+    jp = [encode(rgb, 100, 420)]
+    s = oracle.Scene([EncodedTexture(0, 64, 64, 100, 420, jp)])
+    col = s.decode_level(0)[0, 0]
+    rng = np.random.default_rng(4)
+    g = gb(rng.normal(0, 3, (20, 20)), rng.normal(0, 3, (20, 20)), lod=0.0)
+    for f in (NEAREST, BILINEAR, TRILINEAR):
+        fr, bad = s.resolve(g, f, {0: s.decode_level(0)})
+        assert bad == 0 and (oracle.unpack_frame(fr)[:, :, :3] == col).all()
+
+
+def test_level_selection_and_trilinear_at_integer_lod(small_scene):
+    s = small_scene
+    lv = {L: s.decode_level(L) for L in range(4)}
+    rng = np.random.default_rng(5)
+    u = rng.random((8, 8)).astype(np.float32); v = rng.random((8, 8)).astype(np.float32)
+    for lod, level in ((-3.0, 0), (0.49, 0), (0.5, 1), (1.2, 1), (2.6, 3), (9.0, 3)):
+        a, _ = s.resolve(gb(u, v, lod=lod), BILINEAR, lv)
+        # the same level sampled through a one-level texture
+        one = oracle.Scene([EncodedTexture(0, 0, 0, 0, 0, [s.textures[0].jpegs[level]])])
+        b, _ = one.resolve(gb(u, v), BILINEAR, {0: lv[level]})
+        assert np.array_equal(a, b)
+    for lod in (0.0, 1.0, 2.0):
+        t, _ = s.resolve(gb(u, v, lod=lod), TRILINEAR, lv)
+        b, _ = s.resolve(gb(u, v, lod=lod), BILINEAR, lv)
+        assert np.array_equal(t, b)
+
+
+def test_trilinear_blends_rounded_levels(small_scene):
+    s = small_scene
+    lv = {L: s.decode_level(L) for L in range(4)}
+    rng = np.random.default_rng(6)
+    u = rng.random((6, 6)).astype(np.float32); v = rng.random((6, 6)).astype(np.float32)
+    t, _ = s.resolve(gb(u, v, lod=1.25), TRILINEAR, lv)
+    a, _ = s.resolve(gb(u, v, lod=1.0), TRILINEAR, lv)
+    b, _ = s.resolve(gb(u, v, lod=2.0), TRILINEAR, lv)
+    A = oracle.unpack_frame(a)[..., :3].astype(int); B = oracle.unpack_frame(b)[..., :3].astype(int)
+    assert np.array_equal(oracle.unpack_frame(t)[..., :3], (A * 192 + B * 64 + 128) >> 8)
+
+
+@settings(max_examples=25, deadline=None)
+@given(st.integers(0, 2**31 - 1), st.sampled_from([NEAREST, BILINEAR, TRILINEAR]))
+def test_mark_is_exactly_the_dependency_set(seed, filt):
+    """A block is marked iff the unrounded frame changes when its texels change."""
+    tex = make_textures([(seed, 48, 40, 70, 420, 3)], keep_rgb=False)
+    s = oracle.Scene(tex)
+    rng = np.random.default_rng(seed)
+    g = gb(rng.normal(0.5, 0.7, (4, 4)), rng.normal(0.5, 0.7, (4, 4)), lod=rng.uniform(-0.5, 2.5, (4, 4)))
+    g["lod"] = np.where(rng.random((4, 4)) < 0.3, np.round(g["lod"]), g["lod"])
+    vis, bad = s.mark(g, filt)
+    assert bad == 0
+    base_f = {L: s.decode_level(L, want_f64=True)[1] for L in range(3)}
+    base_b = {L: s.decode_level(L) for L in range(3)}
+    _, f0, _ = s.resolve(g, filt, base_b, base_f, want_f64=True)
+    marked = set(int(b) for b in vis)
+    for b in range(s.n_blocks):
+        L = s.level_of_block(b)
+        r = b - int(s.blk_base[L])
+        if r >= int(s.blk_cols[L] * s.blk_rows[L]):
+            continue
+        bx, by = r % int(s.blk_cols[L]), r // int(s.blk_cols[L])
+        pf = dict(base_f); pf[L] = base_f[L].copy()
+        pf[L][16 * by:16 * by + 16, 16 * bx:16 * bx + 16] += 1000.0
+        _, f1, _ = s.resolve(g, filt, base_b, pf, want_f64=True)
+        assert (np.abs(f1 - f0).max() > 0) == (b in marked), (b, filt)
+
+
+def test_invalid_pixels(small_scene):
+    s = small_scene
+    g = gb([[0.1, np.nan, 0.3, 0.2]], [[0.1, 0.2, np.float32(1e12), 0.2]])
+    g["tex"][0, 3] = 9
+    vis, bad = s.mark(g, BILINEAR)
+    assert bad == 3
+    fr, bad = s.resolve(g, BILINEAR, {L: s.decode_level(L) for L in range(4)})
+    assert bad == 3 and list(fr[0, 1:]) == [oracle.INVALID_TEXEL] * 3
+    g["tex"][0, 0] = oracle.BACKGROUND
+    fr, _ = s.resolve(g, BILINEAR, {})
+    assert fr[0, 0] == 0
+
+
+# ------------------------------------------------------------------ LRU
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.sets(st.integers(0, 40), max_size=12), min_size=1, max_size=12), st.integers(12, 30))
+def test_lru_invariants(frames, cap):
+    sim = oracle.LruSim(cap)
+    resident_prev = set()
+    seen = set()
+    unbounded = oracle.LruSim(10**9)
+    for f, V in enumerate(frames):
+        last_before = dict(sim.last_used)
+        new, ev = sim.step(f, V)
+        R = set(sim.last_used)
+        assert len(R) <= cap
+        assert V <= R
+        assert set(new) == V - resident_prev
+        assert not (set(ev) & V) and set(ev) <= resident_prev
+        kept = (resident_prev - set(ev)) - V
+        for e in ev:                                  # the evicted are the oldest
+            for k in kept:
+                assert (last_before[e], e) < (last_before[k], k)
+        unew, _ = unbounded.step(f, V)
+        assert set(unew) == V - seen
+        seen |= V
+        resident_prev = R
