@@ -1,0 +1,317 @@
+/*
+ * jpt.h -- C ABI of libjpt: on-demand decoding of baseline-JPEG textures
+ * during deferred shading, on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Kristmann, Wimmer, Schuetz, "Variable-Rate Texture
+ * Compression: Real-Time Rendering with JPEG", arXiv 2510.08166):
+ *   - offline, per texture level: an indexing table of MCU offsets and the
+ *     absolute DCs that break the DC prediction chain (Implementation
+ *     details: "Indexing Table" and "Memory Overhead");
+ *   - per frame, after the geometry pass wrote a G-buffer of (uv, texture
+ *     id, mip level): Mark -> Decode -> Resolve -> Update Cache (Method
+ *     section, pass list and subsections "Texture Block Cache", "Mark",
+ *     "Decode", "Resolve", "Update Cache", "Multiple Textures and Mip
+ *     Mapping").
+ *
+ * Conventions
+ *   - Every function returns jpt_status (JPT_OK = 0, errors < 0).
+ *   - The caller owns all memory.  Host outputs go into caller buffers;
+ *     pass NULL outputs to query sizes where stated.  The library never
+ *     allocates device memory.
+ *   - Device calls enqueue work on the caller's HIP stream (`stream` is a
+ *     hipStream_t passed as void*, NULL = the null stream).  They do not
+ *     synchronise, allocate or read device data back, and their launch
+ *     shapes depend only on host arguments, so they can be captured into a
+ *     HIP graph.  Argument errors are returned before anything is enqueued.
+ *     Errors found on the device (corrupt stream, capacity, bad pixel) set
+ *     bits in counters[JPT_CTR_ERROR]; read it after the stream synchronises.
+ *   - No global state; calls on disjoint buffers are thread-safe.
+ *
+ * Terms
+ *   MCU    minimum coded unit: 16x16 texels (4:2:0, six 8x8 data units
+ *          Y00 Y01 Y10 Y11 Cb Cr) or 8x8 texels (4:4:4, Y Cb Cr).
+ *   block  16x16 texels of one (texture, level): one 4:2:0 MCU, or 2x2
+ *          4:4:4 MCUs.  The unit of marking, caching and resolve.
+ *   block id  dense global id: levels are numbered texture by texture, then
+ *          level by level; level L owns [blk_base[L], blk_base[L] +
+ *          blk_cols*blk_rows), block (bx,by) -> blk_base + by*blk_cols + bx,
+ *          blk_cols = ceil(w/16); every blk_base is the previous level's end
+ *          rounded up to a multiple of 32, so each 32-bit word of a block
+ *          bitmask belongs to a single level.  (Generalises the paper's
+ *          MCU id equation and 32-bit cache key of 16/13/3 bits, which
+ *          cannot address 8192^2 textures or more than 8 levels.)
+ *   work item  one MCU to decode, encoded (block id << 2) | q, q = quadrant
+ *          (x + 2y) of a 4:4:4 MCU inside its block, 0 for 4:2:0.  Bit 31
+ *          is set by the decoder on an item whose stream failed to decode.
+ */
+#ifndef JPT_H
+#define JPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JPT_ABI_VERSION 1u
+
+typedef int32_t jpt_status;
+#define JPT_OK 0
+#define JPT_E_ARG (-1)          /* bad argument (NULL, size, enum) */
+#define JPT_E_UNSUPPORTED (-2)  /* valid JPEG outside the baseline subset handled here */
+#define JPT_E_CORRUPT (-3)      /* malformed JPEG / entropy-coded data */
+#define JPT_E_RANGE (-4)        /* a value does not fit the index format */
+#define JPT_E_BUFSIZE (-5)      /* caller buffer too small */
+#define JPT_E_HIP (-6)          /* a HIP runtime call failed */
+#define JPT_E_CAPACITY (-7)     /* scene too large for 32-bit block ids */
+
+#define JPT_SAMPLING_420 420u
+#define JPT_SAMPLING_444 444u
+
+#define JPT_FILTER_NEAREST 0u
+#define JPT_FILTER_BILINEAR 1u
+#define JPT_FILTER_TRILINEAR 2u
+
+#define JPT_CACHE_NONE 0u       /* each frame decodes every visible block; slot = rank */
+#define JPT_CACHE_LRU 1u        /* frame-granular LRU with a slot capacity */
+
+#define JPT_IDCT_MFMA_F16 0u    /* 64x64 basis on MFMA, split-fp16 operands, fp32 accumulate */
+#define JPT_IDCT_SCALAR_F32 1u  /* separable fp32 row/column IDCT on the vector ALUs */
+
+/* counters[] (u32) of a frame */
+#define JPT_CTR_ITEMS 0         /* work items listed this frame (<= max_items) */
+#define JPT_CTR_NEW 1           /* blocks to decode this frame */
+#define JPT_CTR_VISIBLE 2       /* blocks read by this frame */
+#define JPT_CTR_ERROR 3         /* JPT_ERR_* flags */
+#define JPT_CTR_ERROR_ITEM 4    /* smallest failing work-item index (0xFFFFFFFF = none) */
+#define JPT_CTR_EVICTED 5       /* blocks evicted this frame (LRU) */
+#define JPT_CTR_RESIDENT 6      /* resident blocks after this frame (LRU) */
+#define JPT_N_COUNTERS 16u
+
+#define JPT_ERR_CORRUPT 1u      /* invalid code, > 64 coefficients, or MCU span mismatch */
+#define JPT_ERR_CAPACITY 2u     /* work list or cache slots exhausted */
+#define JPT_ERR_PIXEL 4u        /* G-buffer pixel with bad texture id or coordinates */
+
+#define JPT_SLOT_NONE 0xFFFFFFFFu
+#define JPT_TEX_BACKGROUND 0xFFFFFFFFu
+#define JPT_TEXEL_INVALID 0xFFFF00FFu   /* magenta, written for undecodable data */
+
+#define JPT_ITEMS_DU 6u                 /* coefficient stride of a work item, in 8x8 units */
+#define JPT_RECORD_BYTES 64u
+#define JPT_MCUS_PER_RECORD 9u
+#define JPT_STREAM_PAD_WORDS 4u
+
+/* ------------------------------------------------------------------ *
+ * Offline: per-level index (paper: "Indexing Table", "Memory Overhead")
+ * ------------------------------------------------------------------ *
+ * Spliced stream: the level's entropy-coded segment, de-stuffed, with the
+ * DC codes (Huffman code + appended bits) of the first Y, the Cb and the Cr
+ * data unit of every MCU removed (every data unit for 4:4:4).  Those DCs are
+ * stored as absolute values in the records instead; the other Y DCs of a
+ * 4:2:0 MCU stay coded as differences to the previous Y of the same MCU.
+ * Stored as 32-bit words, bit 31 of word 0 is the first bit; followed by
+ * JPT_STREAM_PAD_WORDS zero words.
+ *
+ * Records: one 64-byte record per 9 MCUs (raster order), little-endian:
+ *   bytes 0..3    u32 bit offset of MCU 9g in the spliced stream
+ *   bytes 4..19   u16 rel[8]: offset of MCU 9g+1+i minus that of MCU 9g
+ *   bits 160..483 27 fields of 12 bits (bit b = bit b%8 of byte b/8):
+ *                 field 3j+c = absolute quantised DC of component c
+ *                 (0 Y, 1 Cb, 2 Cr) of MCU 9g+j, two's complement
+ *   bytes 61..63  zero
+ * MCU m spans [start(m), start(m+1)), the last one ends at stream_bits.
+ * Index cost as the paper counts it: (32 + 16*8)/9 bits of offsets plus
+ * 3*12 bits of DCs = 53.78 bits per MCU; the 64-byte record costs 56.9.   */
+typedef struct jpt_level_info {
+    uint32_t width, height;
+    uint32_t sampling;            /* JPT_SAMPLING_420 / _444 */
+    uint32_t mcu_cols, mcu_rows, n_mcu;
+    uint32_t blk_cols, blk_rows;  /* ceil(width/16), ceil(height/16) */
+    uint32_t n_records;           /* ceil(n_mcu / 9) */
+    uint32_t stream_words;        /* words stream_out needs, padding included */
+    uint64_t stream_bits;         /* bits of MCU data in the spliced stream */
+    uint64_t scan_bits;           /* bits of MCU data in the original segment */
+    uint64_t removed_dc_bits;     /* bits of DC codes removed by the splice */
+    uint16_t quant[2][64];        /* zigzag order; [0] luma, [1] chroma */
+    uint8_t huff_bits[4][16];     /* BITS (codes per length 1..16): DC luma, AC luma, DC chroma, AC chroma */
+    uint8_t huff_vals[4][256];    /* HUFFVAL of each table */
+    uint16_t huff_nvals[4];
+    uint16_t reserved0[2];
+    double index_bits_per_mcu;    /* 160/9 */
+    double dc_bits_per_mcu;       /* 36 */
+    double overhead_bpp_bound;    /* (index + dc bits per MCU) / MCU texels */
+    double overhead_bpp_effective;/* same minus the removed DC bits, over the level's MCU texels */
+    double stored_bpp;            /* (records*64*8 + stream_bits) / (width*height) */
+} jpt_level_info;
+
+/* Parse a baseline JPEG (SOF0, 8-bit, 3 components Y Cb Cr with Cb and Cr
+ * sharing quant and Huffman tables, 4:2:0 or 4:4:4, one interleaved scan,
+ * no restart interval) and build the spliced stream and records.
+ *   jpeg/len       host bytes of the file (read only)
+ *   info           host, filled on JPT_OK (and on JPT_E_BUFSIZE)
+ *   stream_out     host, >= info->stream_words u32, or NULL to query
+ *   records_out    host, >= info->n_records * 64 bytes, or NULL to query
+ * Errors: JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT (any MCU fails to
+ * decode), JPT_E_RANGE (an absolute DC outside 12 bits, a relative offset
+ * above 65535 bits, stream above 2^32-1 bits), JPT_E_BUFSIZE. */
+jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level_info *info, uint32_t *stream_out,
+                           size_t stream_cap_words, uint8_t *records_out, size_t records_cap_bytes);
+
+/* Decode tables for the GPU entropy decoder, built from info's Huffman
+ * tables (the paper's per-code matching loop replaced by table lookup).
+ * tables_out: host, JPT_TABLESET_WORDS u32 (or NULL to query *words).
+ * Errors: JPT_E_ARG, JPT_E_CORRUPT (over-full code), JPT_E_BUFSIZE. */
+#define JPT_TABLESET_WORDS 4608u
+jpt_status jpt_build_tables(const jpt_level_info *info, uint32_t *tables_out, size_t cap_words, size_t *words);
+
+/* Block-id layout of a scene (see "block id" above).  infos: n_levels
+ * level infos in scene order.  blk_base: host, n_levels u32.  word_level:
+ * host, one u32 per bitmask word (= *n_blocks / 32), the level owning that
+ * word; NULL to query.  Errors: JPT_E_ARG, JPT_E_CAPACITY (more than 2^29
+ * block ids), JPT_E_BUFSIZE. */
+jpt_status jpt_layout(const jpt_level_info *infos, uint32_t n_levels, uint32_t *blk_base, uint32_t *word_level,
+                      size_t word_level_cap, uint32_t *n_blocks);
+
+/* ------------------------------------------------------------------ *
+ * Device-side descriptors (arrays of these live in device memory)
+ * ------------------------------------------------------------------ */
+typedef struct jpt_level_desc {   /* 64 bytes */
+    uint64_t stream;              /* device address of the spliced stream (u32 words) */
+    uint64_t records;             /* device address of the 64-byte records */
+    uint64_t stream_bits;
+    uint32_t width, height;
+    uint32_t blk_cols, blk_rows;
+    uint32_t mcu_cols, n_mcu;
+    uint32_t blk_base;
+    uint32_t sampling;            /* 420 / 444 */
+    uint32_t table_set;           /* index into jpt_scene.tables */
+    uint32_t quant;               /* index into jpt_scene.quant */
+} jpt_level_desc;
+
+typedef struct jpt_texture_desc { /* 16 bytes */
+    uint32_t first_level;         /* index of level 0 in the level array */
+    uint32_t n_levels;
+    uint32_t width, height;       /* of level 0 */
+} jpt_texture_desc;
+
+/* Fill a level descriptor from an index build (host helper). */
+jpt_status jpt_make_level_desc(const jpt_level_info *info, uint64_t stream_dptr, uint64_t records_dptr,
+                               uint32_t blk_base, uint32_t table_set, uint32_t quant_index, jpt_level_desc *out);
+
+/* One G-buffer pixel (16 bytes): texture coordinates with repeat
+ * addressing (v = 0 is the top texel row), texture id (JPT_TEX_BACKGROUND
+ * for none) and level of detail log2(texels per pixel).  Texel
+ * coordinates: nearest s = u*w, texel floor(s) mod w; linear
+ * s = u*w - 0.5, texels floor(s), floor(s)+1 with weights 256-f, f,
+ * f = floor(frac(s)*256 + 0.5); every product and sum a separate fp32
+ * operation.  Level: nearest/linear clamp(floor(lod + 0.5), 0, n-1);
+ * trilinear floor(lod) and the next level with weights 256-t, t,
+ * t = floor(frac(lod)*256 + 0.5) (one level if lod < 0 or lod >= n-1).
+ * Taps of zero weight are neither marked nor read.  A pixel with a bad
+ * texture id, a non-finite field or |s| >= 2^30 is invalid. */
+typedef struct jpt_gpixel { float u, v; uint32_t tex; float lod; } jpt_gpixel;
+
+typedef struct jpt_scene {        /* host struct holding device pointers */
+    const jpt_level_desc *levels;     /* n_levels */
+    const jpt_texture_desc *textures; /* n_textures */
+    const uint32_t *word_level;       /* n_blocks / 32 */
+    const uint32_t *tables;           /* n_tablesets * JPT_TABLESET_WORDS */
+    const uint16_t *quant;            /* n_quant * 128, zigzag, [luma 64][chroma 64] */
+    uint32_t n_levels, n_textures, n_tablesets, n_quant;
+    uint32_t n_blocks;                /* multiple of 32, <= 2^29 */
+    uint32_t reserved;
+} jpt_scene;
+
+typedef struct jpt_view {         /* host struct holding device pointers */
+    const jpt_gpixel *gbuf;       /* height rows of pitch pixels */
+    uint32_t *frame;              /* height rows of frame_pitch u32 (RGBA8, R low byte, A 255) */
+    uint32_t width, height;
+    uint32_t pitch, frame_pitch;
+} jpt_view;
+
+typedef struct jpt_frame {        /* per-frame device scratch, caller-allocated */
+    uint32_t *vis;                /* n_blocks/32 words: blocks this frame reads */
+    uint32_t *work;               /* max_items work items, ascending */
+    uint32_t *counters;           /* JPT_N_COUNTERS */
+    uint64_t *scan;               /* jpt_scan_entries(n_blocks) entries */
+    int16_t *coef;                /* max_items * 6 * 64 quantised coefficients, zigzag order */
+    uint32_t max_items;
+    uint32_t frame_no;            /* LRU timestamp of this frame */
+} jpt_frame;
+
+typedef struct jpt_cache {        /* decoded-block cache, caller-allocated */
+    uint32_t *texels;             /* n_slots * 256 RGBA8 texels, slot-major, 16x16 row-major */
+    uint32_t *slot_of;            /* n_blocks: slot of each block (valid while resident) */
+    uint32_t *owner;              /* n_slots: block in each slot or JPT_SLOT_NONE (LRU) */
+    uint32_t *last_used;          /* n_slots: frame_no of last use (LRU) */
+    uint32_t *resident;           /* n_blocks/32 words: resident blocks (LRU) */
+    uint32_t n_slots;
+    uint32_t policy;              /* JPT_CACHE_NONE / JPT_CACHE_LRU */
+} jpt_cache;
+
+typedef struct jpt_tuning {       /* launch knobs; NULL = defaults */
+    uint32_t decode_groups;       /* persistent workgroups of the decode kernels (0 = auto) */
+    uint32_t idct_groups;         /* persistent workgroups of the IDCT kernel (0 = auto) */
+    uint32_t reserved[6];
+} jpt_tuning;
+
+/* Entries of jpt_frame.scan for a scene of n_blocks block ids. */
+uint32_t jpt_scan_entries(uint32_t n_blocks);
+
+/* ------------------------------------------------------------------ *
+ * Per frame
+ * ------------------------------------------------------------------ */
+
+/* Mark + compact (paper: Mark; decode queue of the overview figure; the
+ * cache's visibility flags).  Clears frame->vis and frame->counters, marks
+ * every block a pixel of any view reads with non-zero weight under
+ * `filter`, then lists the blocks not yet resident as work items in
+ * ascending block-id order and assigns their cache slots:
+ *   JPT_CACHE_NONE: slot = rank of the block among this frame's new blocks
+ *     (blocks beyond n_slots get JPT_SLOT_NONE and raise JPT_ERR_CAPACITY);
+ *   JPT_CACHE_LRU: visible resident blocks get last_used = frame_no; new
+ *     blocks take free slots, else evict the resident blocks not visible this
+ *     frame with the smallest (last_used, block id).
+ * cache may be NULL only if nothing reads slots (block lists only).
+ * Errors: JPT_E_ARG (NULL/short buffers, filter, view sizes), JPT_E_HIP. */
+jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                           jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+/* Decode (paper: Decode).  For every work item listed by the last
+ * jpt_mark_blocks on this frame: entropy-decode the MCU through the index
+ * into frame->coef (zigzag order, stride 6*64 per item), then dequantise,
+ * inverse-DCT, convert YCbCr (JFIF, chroma replicated) to RGB with a
+ * single rounding, and store RGBA8 texels into the block's cache slot.
+ * A failed item gets bit 31 in frame->work, JPT_ERR_CORRUPT and
+ * JPT_TEXEL_INVALID texels.  idct_mode: JPT_IDCT_*.
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_decode_blocks(const jpt_scene *scene, jpt_frame *frame, jpt_cache *cache, uint32_t idct_mode,
+                             const jpt_tuning *tuning, void *stream);
+
+/* Entropy decode only (the first half of jpt_decode_blocks): fills
+ * frame->coef for the listed work items.  Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_entropy_decode(const jpt_scene *scene, jpt_frame *frame, const jpt_tuning *tuning, void *stream);
+
+/* The second half of jpt_decode_blocks: dequantise, IDCT, colour-convert
+ * and store the texels of the listed work items from frame->coef (filled by
+ * jpt_entropy_decode).  Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *cache, uint32_t idct_mode,
+                          const jpt_tuning *tuning, void *stream);
+
+/* Resolve (paper: Resolve): every pixel of every view reads its filter taps
+ * from the cache slots of their blocks and writes the filtered RGBA8 value
+ * (integer weights: bilinear (sum t*w + 32768) >> 16 per channel,
+ * trilinear (a*(256-t) + b*t + 128) >> 8).  Background pixels get 0;
+ * invalid pixels and taps in blocks without a slot get JPT_TEXEL_INVALID.
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                       const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+uint32_t jpt_version(void);
+const char *jpt_status_string(jpt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JPT_H */

@@ -1,0 +1,448 @@
+// Decode (paper: Method, "Decode"; Implementation details, "Warp-Level
+// Parallel Huffman Decoding").
+//
+// k_entropy: one lane per MCU.  The paper gives each MCU a 64-thread block
+// that matches codes with a warp ballot; on wave64 hardware that leaves 63
+// lanes idle per symbol, so here a lane walks its own MCU's symbol chain with
+// a 10-bit lookup table in LDS (code, run, size and, when they fit, the
+// appended value bits in one entry) and a canonical fallback for longer
+// codes.  Coefficients go to a per-lane LDS tile (6 x 64 int16, zigzag
+// order), which the wave then copies to HBM with coalesced 16-byte stores.
+//
+// k_idct_mfma: dequantise and inverse-DCT every 8x8 unit as one 64x64
+// contraction X = K F (K = basis with its columns in zigzag order) on the
+// matrix cores (v_mfma_f32_32x32x16_f16), 32 units per column tile.  K is
+// split into fp16 hi + lo parts (lo scaled by 2^11) accumulated in fp32;
+// F (integer, |F| <= 2048 for real encoders) is exact in fp16, and larger
+// values take an exact hi/lo split of F as well.  Then +128, clamp,
+// chroma replication and JFIF YCbCr -> RGB with one rounding, RGBA8 into
+// the block's cache slot.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+constexpr int kItemCoefs = JPT_ITEMS_DU * 64;  // int16 per work item
+
+__device__ __forceinline__ int sext12(uint32_t v) { return (int)(v << 20) >> 20; }
+__device__ __forceinline__ uint32_t rec_rel(const uint32_t *rec, uint32_t i) {
+    return (rec[1 + (i >> 1)] >> ((i & 1) * 16)) & 0xFFFFu;
+}
+
+// ------------------------------------------------------------- entropy
+template <bool kLdsTables>
+__global__ __launch_bounds__(64) void k_entropy(const jpt_level_desc *__restrict__ levels,
+                                                const uint32_t *__restrict__ word_level,
+                                                const uint32_t *__restrict__ tables, uint32_t *__restrict__ work,
+                                                uint32_t *__restrict__ counters, int16_t *__restrict__ coef) {
+    __shared__ uint32_t s_tab[kLdsTables ? JPT_TABLESET_WORDS : 1];
+    __shared__ __attribute__((aligned(16))) int16_t s_coef[64 * kItemCoefs];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t n_items = counters[JPT_CTR_ITEMS];
+    if (blockIdx.x * 64u >= n_items) return;
+    if (kLdsTables)
+        for (uint32_t i = lane; i < JPT_TABLESET_WORDS; i += 64) s_tab[i] = tables[i];
+
+    for (uint32_t chunk = blockIdx.x; chunk * 64u < n_items; chunk += gridDim.x) {
+        int4 *z = reinterpret_cast<int4 *>(s_coef);
+        for (uint32_t i = lane; i < 64u * kItemCoefs / 8u; i += 64) z[i] = make_int4(0, 0, 0, 0);
+        __syncthreads();
+        const uint32_t item = chunk * 64u + lane;
+        if (item < n_items) {
+            const uint32_t w = work[item];
+            const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
+            const jpt_level_desc *L = levels + word_level[b >> 5];
+            const uint32_t blk_base = L->blk_base, blk_cols = L->blk_cols, mcu_cols = L->mcu_cols;
+            const uint32_t n_mcu = L->n_mcu, sampling = L->sampling;
+            const uint32_t *__restrict__ stream = reinterpret_cast<const uint32_t *>(L->stream);
+            const uint32_t *__restrict__ recs = reinterpret_cast<const uint32_t *>(L->records);
+            const uint32_t stream_bits = (uint32_t)L->stream_bits;
+            const uint32_t *__restrict__ tab = kLdsTables ? s_tab : tables + (size_t)L->table_set * JPT_TABLESET_WORDS;
+            const uint32_t r = b - blk_base, by = r / blk_cols, bx = r - by * blk_cols;
+            bool present = true;
+            uint32_t mcu;
+            if (sampling == JPT_SAMPLING_444) {
+                const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
+                present = mx < mcu_cols && my < n_mcu / mcu_cols;
+                mcu = my * mcu_cols + mx;
+            } else {
+                mcu = by * mcu_cols + bx;
+            }
+            if (present) {
+                const uint32_t g = mcu / 9, j = mcu - g * 9;
+                const uint32_t *rec = recs + (size_t)g * 16;
+                const uint32_t anchor = rec[0];
+                const uint32_t start = anchor + (j ? rec_rel(rec, j - 1) : 0u);
+                const uint32_t end = (mcu + 1 >= n_mcu) ? stream_bits : (j < 8 ? anchor + rec_rel(rec, j) : rec[16]);
+                const uint32_t bp = 160 + 36 * j;
+                const uint64_t dv = ((((uint64_t)rec[(bp >> 5) + 1]) << 32) | rec[bp >> 5]) >> (bp & 31);
+                const int dc0 = sext12((uint32_t)dv & 0xFFFu), dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu),
+                          dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
+                const uint32_t limit = ((stream_bits + 31) >> 5) + JPT_STREAM_PAD_WORDS;
+
+                int16_t *cf = s_coef + lane * kItemCoefs;
+                uint32_t wp = start >> 5;
+                const uint32_t sh0 = start & 31;
+                uint64_t buf = ((((uint64_t)stream[wp]) << 32) | (wp + 1 < limit ? stream[wp + 1] : 0u)) << sh0;
+                int nb = 64 - (int)sh0;
+                wp += 2;
+                uint32_t nxt = wp < limit ? stream[wp] : 0u;
+                uint32_t pos = start;
+                const int ndu = sampling == JPT_SAMPLING_444 ? 3 : 6;
+                int du = 0, k = 1, comp = 0, ypred = dc0;
+                uint32_t tsel = 1;  // AC luma
+                cf[0] = (int16_t)dc0;
+                bool ok = true, done = false;
+                for (int it = 0; it < 6 * 64 + 8; ++it) {
+                    if (nb < 32) {
+                        buf |= (uint64_t)nxt << (32 - nb);
+                        nb += 32;
+                        ++wp;
+                        nxt = wp < limit ? stream[wp] : 0u;
+                    }
+                    const uint32_t peek = (uint32_t)(buf >> 32);
+                    uint32_t e = tab[tsel * JPT_FAST_SIZE + (peek >> (32 - JPT_FAST_BITS))];
+                    uint32_t len = e & 31u;
+                    int size, run;
+                    if (len == 0) {
+                        if (e & JPT_FE_BAD) { ok = false; break; }
+                        // canonical search over code lengths 11..16
+                        const uint32_t *sl = tab + JPT_SLOW_OFFSET + tsel * JPT_SLOW_WORDS;
+                        uint32_t code = 0;
+                        for (int c = JPT_FAST_BITS + 1; c <= 16; c++) {
+                            code = peek >> (32 - c);
+                            if ((int)code <= (int)sl[c]) { len = (uint32_t)c; break; }
+                        }
+                        if (len == 0) { ok = false; break; }
+                        const uint32_t si = code + sl[17 + len];
+                        const uint32_t sym = (sl[34 + ((si >> 2) & 63)] >> ((si & 3) * 8)) & 0xFFu;
+                        if (tsel & 1) {
+                            run = (int)(sym >> 4); size = (int)(sym & 15);
+                            if (size > 10 || (size == 0 && run != 0 && run != 15)) { ok = false; break; }
+                        } else {
+                            run = 0; size = (int)sym;
+                            if (size > 11) { ok = false; break; }
+                        }
+                        e = 0;
+                    } else {
+                        size = (int)((e >> 6) & 15u);
+                        run = (int)((e >> 10) & 15u);
+                    }
+                    int value;
+                    uint32_t used;
+                    if (e & JPT_FE_FUSED) {
+                        used = len;
+                        value = (int)e >> 16;
+                    } else {
+                        const uint32_t extra = size ? ((peek << len) >> (32 - size)) : 0u;
+                        value = (size && extra < (1u << (size - 1))) ? (int)extra - (1 << size) + 1 : (int)extra;
+                        used = len + (uint32_t)size;
+                    }
+                    buf <<= used;
+                    nb -= (int)used;
+                    pos += used;
+                    if (pos > end) { ok = false; break; }
+                    if (k == 0) {  // difference DC of Y data units 1..3 (4:2:0)
+                        ypred += value;
+                        if (ypred < -32768 || ypred > 32767) { ok = false; break; }
+                        cf[du * 64] = (int16_t)ypred;
+                        k = 1;
+                    } else if (size == 0) {
+                        k = run == 15 ? k + 16 : 64;  // ZRL or EOB
+                    } else {
+                        k += run;
+                        if (k > 63) { ok = false; break; }
+                        cf[du * 64 + k] = (int16_t)value;
+                        ++k;
+                    }
+                    if (k >= 64) {
+                        if (k > 64) { ok = false; break; }
+                        if (++du >= ndu) { done = true; break; }
+                        comp = sampling == JPT_SAMPLING_444 ? du : (du < 4 ? 0 : du - 3);
+                        if (comp != 0) {
+                            cf[du * 64] = (int16_t)(comp == 1 ? dc1 : dc2);
+                            k = 1;
+                            tsel = 3;
+                        } else {
+                            k = 0;
+                            tsel = 0;
+                        }
+                    } else {
+                        tsel = (comp ? 2u : 0u) + (k != 0 ? 1u : 0u);
+                    }
+                }
+                if (!(done && ok && pos == end)) {
+                    atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CORRUPT);
+                    atomicMin(counters + JPT_CTR_ERROR_ITEM, item);
+                    work[item] = w | 0x80000000u;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t n_valid = min(64u, n_items - chunk * 64u);
+        int4 *dst = reinterpret_cast<int4 *>(coef + (size_t)chunk * 64u * kItemCoefs);
+        for (uint32_t i = lane; i < n_valid * (kItemCoefs / 8u); i += 64) dst[i] = z[i];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- IDCT
+// zigzag scan position -> natural index (row = vertical frequency),
+// generated by walking the anti-diagonals of the 8x8 block.
+struct ZigZag {
+    uint8_t nat[64];
+};
+constexpr ZigZag make_zigzag() {
+    ZigZag z{};
+    int i = 0;
+    for (int d = 0; d < 15; d++) {
+        const int lo = d < 8 ? 0 : d - 7, hi = d < 8 ? d : 7;
+        if (d & 1)
+            for (int r = lo; r <= hi; r++) z.nat[i++] = (uint8_t)(r * 8 + d - r);
+        else
+            for (int r = hi; r >= lo; r--) z.nat[i++] = (uint8_t)(r * 8 + d - r);
+    }
+    return z;
+}
+__constant__ ZigZag kZigZag = make_zigzag();
+
+// cos(k pi / 16) for k = 0..8, correctly rounded fp32
+__device__ __forceinline__ float cos16(int k) {
+    const float c[9] = {1.0f, 0.980785280403230f, 0.923879532511287f, 0.831469612302545f, 0.707106781186548f,
+                        0.555570233019602f, 0.382683432365090f, 0.195090322016128f, 0.0f};
+    k &= 31;
+    if (k > 16) k = 32 - k;
+    return k > 8 ? -c[16 - k] : c[k];
+}
+// half the 1-D basis: C(u)/2 cos((2x+1) u pi / 16), C(0) = 1/sqrt(2)
+__device__ __forceinline__ float basis1d(int u, int x) { return u == 0 ? 0.5f * cos16(4) : 0.5f * cos16((2 * x + 1) * u); }
+
+__device__ __forceinline__ uint32_t to_u8(float v) {
+    float r = floorf(v + 0.5f);
+    r = fminf(fmaxf(r, 0.0f), 255.0f);
+    return (uint32_t)r;
+}
+__device__ __forceinline__ uint32_t ycc_to_rgba(float Y, float Cb, float Cr) {
+    const float cb = Cb - 128.0f, cr = Cr - 128.0f;
+    const uint32_t R = to_u8(Y + 1.402f * cr);
+    const uint32_t G = to_u8(Y - 0.344136f * cb - 0.714136f * cr);
+    const uint32_t B = to_u8(Y + 1.772f * cb);
+    return R | (G << 8) | (B << 16) | 0xFF000000u;
+}
+
+constexpr int kIdctItems = 16;                       // items per wave iteration
+constexpr int kIdctUnits = kIdctItems * JPT_ITEMS_DU;  // 96 = 3 column tiles of 32
+
+__global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restrict__ levels,
+                                                  const uint32_t *__restrict__ word_level,
+                                                  const uint16_t *__restrict__ quant, const uint32_t *__restrict__ work,
+                                                  const uint32_t *__restrict__ counters,
+                                                  const int16_t *__restrict__ coef,
+                                                  const uint32_t *__restrict__ slot_of,
+                                                  uint32_t *__restrict__ texels) {
+    __shared__ float s_samp[kIdctUnits * 64];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t n_items = counters[JPT_CTR_ITEMS];
+    if (blockIdx.x * (uint32_t)kIdctItems >= n_items) return;
+    const uint32_t col = lane & 31, half = lane >> 5;
+
+    // basis operands: A[m][s] holds K[32m + col][16s + 8 half + t], t = 0..7
+    half8 Khi[2][4], Klo[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; m++)
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int i = 32 * m + (int)col;            // pixel y*8+x
+                const int n = kZigZag.nat[16 * s + 8 * half + t];  // natural v*8+u
+                const float K = basis1d(n & 7, i & 7) * basis1d(n >> 3, i >> 3);
+                const _Float16 hi = (_Float16)K;
+                Khi[m][s][t] = hi;
+                Klo[m][s][t] = (_Float16)((K - (float)hi) * 2048.0f);
+            }
+
+    for (uint32_t base = blockIdx.x * kIdctItems; base < n_items; base += gridDim.x * kIdctItems) {
+#pragma unroll
+        for (int ct = 0; ct < kIdctUnits / 32; ct++) {
+            const uint32_t d = 32 * ct + col;
+            const uint32_t it = base + d / JPT_ITEMS_DU, du = d % JPT_ITEMS_DU;
+            int fv[4][8];
+            bool wide = false;
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int t = 0; t < 8; t++) fv[s][t] = 0;
+            if (it < n_items) {
+                const uint32_t b = (work[it] & 0x7FFFFFFFu) >> 2;
+                const jpt_level_desc *L = levels + word_level[b >> 5];
+                const bool s444 = L->sampling == JPT_SAMPLING_444;
+                if (!(s444 && du >= 3)) {
+                    const int comp = s444 ? (int)du : (du < 4 ? 0 : 1);
+                    const uint16_t *qt = quant + (size_t)L->quant * 128 + (comp ? 64 : 0);
+                    const int16_t *cp = coef + (size_t)it * kItemCoefs + du * 64;
+#pragma unroll
+                    for (int s = 0; s < 4; s++) {
+                        const int4 cv = *reinterpret_cast<const int4 *>(cp + 16 * s + 8 * half);
+                        const uint4 qv = *reinterpret_cast<const uint4 *>(qt + 16 * s + 8 * half);
+                        const int32_t cw[4] = {cv.x, cv.y, cv.z, cv.w};
+                        const uint32_t qw[4] = {qv.x, qv.y, qv.z, qv.w};
+#pragma unroll
+                        for (int p = 0; p < 4; p++) {
+                            const int c0 = (int)(int16_t)(cw[p] & 0xFFFF), c1 = cw[p] >> 16;
+                            const int q0 = (int)(qw[p] & 0xFFFFu), q1 = (int)(qw[p] >> 16);
+                            fv[s][2 * p] = c0 * q0;
+                            fv[s][2 * p + 1] = c1 * q1;
+                        }
+#pragma unroll
+                        for (int t = 0; t < 8; t++) wide |= (fv[s][t] > 2048 || fv[s][t] < -2048);
+                    }
+                }
+            }
+            const bool any_wide = __ballot(wide) != 0;
+            half8 Fh[4], Fl[4];
+#pragma unroll
+            for (int s = 0; s < 4; s++)
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    if (!any_wide) {
+                        Fh[s][t] = (_Float16)(float)fv[s][t];
+                        Fl[s][t] = (_Float16)0.0f;
+                    } else {  // F = 128 * (F >> 7) + (F & 127), both parts exact in fp16
+                        Fh[s][t] = (_Float16)(float)(fv[s][t] >> 7);
+                        Fl[s][t] = (_Float16)(float)(fv[s][t] & 127);
+                    }
+                }
+#pragma unroll
+            for (int m = 0; m < 2; m++) {
+                float16v ah = {}, al = {};
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    ah = __builtin_amdgcn_mfma_f32_32x32x16_f16(Khi[m][s], Fh[s], ah, 0, 0, 0);
+                    al = __builtin_amdgcn_mfma_f32_32x32x16_f16(Klo[m][s], Fh[s], al, 0, 0, 0);
+                }
+                float16v X;
+                if (!any_wide) {
+                    X = ah + al * (1.0f / 2048.0f);
+                } else {
+                    float16v bh = {}, bl = {};
+#pragma unroll
+                    for (int s = 0; s < 4; s++) {
+                        bh = __builtin_amdgcn_mfma_f32_32x32x16_f16(Khi[m][s], Fl[s], bh, 0, 0, 0);
+                        bl = __builtin_amdgcn_mfma_f32_32x32x16_f16(Klo[m][s], Fl[s], bl, 0, 0, 0);
+                    }
+                    X = (ah + al * (1.0f / 2048.0f)) * 128.0f + (bh + bl * (1.0f / 2048.0f));
+                }
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    const int row = 8 * (r >> 2) + 4 * (int)half + (r & 3);
+                    const float v = fminf(fmaxf(X[r] + 128.0f, 0.0f), 255.0f);
+                    s_samp[d * 64 + 32 * m + row] = v;
+                }
+            }
+        }
+        __syncthreads();
+        // colour conversion and store, one item at a time (1 KiB per 4:2:0 item)
+        for (int li = 0; li < kIdctItems; li++) {
+            const uint32_t it = base + li;
+            if (it >= n_items) break;
+            const uint32_t w = work[it];
+            const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
+            const bool failed = (w >> 31) != 0;
+            const uint32_t slot = slot_of[b];
+            if (slot == JPT_SLOT_NONE) continue;
+            const jpt_level_desc *L = levels + word_level[b >> 5];
+            const float *sp = s_samp + li * JPT_ITEMS_DU * 64;
+            uint32_t *dst = texels + (size_t)slot * 256;
+            if (L->sampling != JPT_SAMPLING_444) {
+                const uint32_t ty = lane >> 2, tx0 = (lane & 3) * 4;
+                uint32_t o[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const uint32_t tx = tx0 + i;
+                    const float Y = sp[((ty >> 3) * 2 + (tx >> 3)) * 64 + (ty & 7) * 8 + (tx & 7)];
+                    const float Cb = sp[4 * 64 + (ty >> 1) * 8 + (tx >> 1)];
+                    const float Cr = sp[5 * 64 + (ty >> 1) * 8 + (tx >> 1)];
+                    o[i] = failed ? JPT_TEXEL_INVALID : ycc_to_rgba(Y, Cb, Cr);
+                }
+                *reinterpret_cast<uint4 *>(dst + ty * 16 + tx0) = make_uint4(o[0], o[1], o[2], o[3]);
+            } else if (lane < 16) {
+                const uint32_t r = b - L->blk_base, by = r / L->blk_cols, bx = r - by * L->blk_cols;
+                const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
+                if (mx < L->mcu_cols && my < L->n_mcu / L->mcu_cols) {
+                    const uint32_t ty = lane >> 1, tx0 = (lane & 1) * 4;
+                    uint32_t o[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const uint32_t p = ty * 8 + tx0 + i;
+                        o[i] = failed ? JPT_TEXEL_INVALID : ycc_to_rgba(sp[p], sp[64 + p], sp[128 + p]);
+                    }
+                    *reinterpret_cast<uint4 *>(dst + (8 * (q >> 1) + ty) * 16 + 8 * (q & 1) + tx0) =
+                        make_uint4(o[0], o[1], o[2], o[3]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+uint32_t default_groups(const jpt_tuning *t, bool idct) {
+    uint32_t g = t ? (idct ? t->idct_groups : t->decode_groups) : 0u;
+    return g ? g : (idct ? 2048u : 512u);
+}
+
+jpt_status launch_entropy(const jpt_scene *scene, jpt_frame *frame, const jpt_tuning *tuning, hipStream_t st) {
+    const uint32_t groups = default_groups(tuning, false);
+    if (scene->n_tablesets == 1)
+        hipLaunchKernelGGL(k_entropy<true>, dim3(groups), dim3(64), 0, st, scene->levels, scene->word_level,
+                           scene->tables, frame->work, frame->counters, frame->coef);
+    else
+        hipLaunchKernelGGL(k_entropy<false>, dim3(groups), dim3(64), 0, st, scene->levels, scene->word_level,
+                           scene->tables, frame->work, frame->counters, frame->coef);
+    HIP_CHECK_LAUNCH();
+    return JPT_OK;
+}
+
+jpt_status check_args(const jpt_scene *scene, const jpt_frame *frame) {
+    if (!scene || !frame) return JPT_E_ARG;
+    if (!scene->levels || !scene->word_level || !scene->tables || !scene->quant || scene->n_tablesets == 0)
+        return JPT_E_ARG;
+    if (!frame->work || !frame->counters || !frame->coef) return JPT_E_ARG;
+    return JPT_OK;
+}
+
+}  // namespace
+
+extern "C" jpt_status jpt_entropy_decode(const jpt_scene *scene, jpt_frame *frame, const jpt_tuning *tuning,
+                                         void *stream) {
+    jpt_status s = check_args(scene, frame);
+    if (s) return s;
+    return launch_entropy(scene, frame, tuning, (hipStream_t)stream);
+}
+
+extern "C" jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *cache, uint32_t idct_mode,
+                                     const jpt_tuning *tuning, void *stream) {
+    jpt_status s = check_args(scene, frame);
+    if (s) return s;
+    if (!cache || !cache->texels || !cache->slot_of) return JPT_E_ARG;
+    if (idct_mode != JPT_IDCT_MFMA_F16) return JPT_E_ARG;
+    hipLaunchKernelGGL(k_idct_mfma, dim3(default_groups(tuning, true)), dim3(64), 0, (hipStream_t)stream,
+                       scene->levels, scene->word_level, scene->quant, frame->work, frame->counters, frame->coef,
+                       cache->slot_of, cache->texels);
+    HIP_CHECK_LAUNCH();
+    return JPT_OK;
+}
+
+extern "C" jpt_status jpt_decode_blocks(const jpt_scene *scene, jpt_frame *frame, jpt_cache *cache,
+                                        uint32_t idct_mode, const jpt_tuning *tuning, void *stream) {
+    jpt_status s = check_args(scene, frame);
+    if (s) return s;
+    if (!cache || !cache->texels || !cache->slot_of) return JPT_E_ARG;
+    if (idct_mode != JPT_IDCT_MFMA_F16) return JPT_E_ARG;
+    if ((s = launch_entropy(scene, frame, tuning, (hipStream_t)stream))) return s;
+    return jpt_idct_color(scene, frame, cache, idct_mode, tuning, stream);
+}

@@ -1,0 +1,412 @@
+"""Python binding of libjpt (include/jpt.h): argument marshalling only.
+
+Every step of the per-frame path runs in the HIP kernels of libjpt.so; this
+module builds the host-side descriptors, owns device memory through torch
+tensors, and passes raw pointers and the current HIP stream to the C ABI.
+If libjpt.so is missing the import of the library fails loudly (there is no
+fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libjpt.so")
+
+u8, u16, u32, u64, f64, vp = (ctypes.c_uint8, ctypes.c_uint16, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                              ctypes.c_void_p)
+
+JPT_OK, JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT, JPT_E_RANGE, JPT_E_BUFSIZE, JPT_E_HIP, JPT_E_CAPACITY = \
+    0, -1, -2, -3, -4, -5, -6, -7
+FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR = 0, 1, 2
+CACHE_NONE, CACHE_LRU = 0, 1
+IDCT_MFMA_F16, IDCT_SCALAR_F32 = 0, 1
+CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT = range(7)
+N_COUNTERS = 16
+ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL = 1, 2, 4
+SLOT_NONE = 0xFFFFFFFF
+TEXEL_INVALID = 0xFFFF00FF
+ITEM_COEFS = 6 * 64
+RECORD_BYTES = 64
+TABLESET_WORDS = 4608
+
+
+class LevelInfo(ctypes.Structure):
+    _fields_ = [("width", u32), ("height", u32), ("sampling", u32), ("mcu_cols", u32), ("mcu_rows", u32),
+                ("n_mcu", u32), ("blk_cols", u32), ("blk_rows", u32), ("n_records", u32), ("stream_words", u32),
+                ("stream_bits", u64), ("scan_bits", u64), ("removed_dc_bits", u64),
+                ("quant", (u16 * 64) * 2), ("huff_bits", (u8 * 16) * 4), ("huff_vals", (u8 * 256) * 4),
+                ("huff_nvals", u16 * 4), ("reserved0", u16 * 2),
+                ("index_bits_per_mcu", f64), ("dc_bits_per_mcu", f64), ("overhead_bpp_bound", f64),
+                ("overhead_bpp_effective", f64), ("stored_bpp", f64)]
+
+
+class LevelDesc(ctypes.Structure):
+    _fields_ = [("stream", u64), ("records", u64), ("stream_bits", u64), ("width", u32), ("height", u32),
+                ("blk_cols", u32), ("blk_rows", u32), ("mcu_cols", u32), ("n_mcu", u32), ("blk_base", u32),
+                ("sampling", u32), ("table_set", u32), ("quant", u32)]
+
+
+class TextureDesc(ctypes.Structure):
+    _fields_ = [("first_level", u32), ("n_levels", u32), ("width", u32), ("height", u32)]
+
+
+class SceneC(ctypes.Structure):
+    _fields_ = [("levels", vp), ("textures", vp), ("word_level", vp), ("tables", vp), ("quant", vp),
+                ("n_levels", u32), ("n_textures", u32), ("n_tablesets", u32), ("n_quant", u32),
+                ("n_blocks", u32), ("reserved", u32)]
+
+
+class ViewC(ctypes.Structure):
+    _fields_ = [("gbuf", vp), ("frame", vp), ("width", u32), ("height", u32), ("pitch", u32),
+                ("frame_pitch", u32)]
+
+
+class FrameC(ctypes.Structure):
+    _fields_ = [("vis", vp), ("work", vp), ("counters", vp), ("scan", vp), ("coef", vp), ("max_items", u32),
+                ("frame_no", u32)]
+
+
+class CacheC(ctypes.Structure):
+    _fields_ = [("texels", vp), ("slot_of", vp), ("owner", vp), ("last_used", vp), ("resident", vp),
+                ("n_slots", u32), ("policy", u32)]
+
+
+class TuningC(ctypes.Structure):
+    _fields_ = [("decode_groups", u32), ("idct_groups", u32), ("reserved", u32 * 6)]
+
+
+assert ctypes.sizeof(LevelDesc) == 64 and ctypes.sizeof(TextureDesc) == 16
+assert ctypes.sizeof(SceneC) == 64 and ctypes.sizeof(ViewC) == 32 and ctypes.sizeof(FrameC) == 48
+
+# name -> (restype, argtypes) of every function the header declares
+SIGNATURES = {
+    "jpt_build_index": (ctypes.c_int32, [vp, ctypes.c_size_t, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]),
+    "jpt_build_tables": (ctypes.c_int32, [vp, vp, ctypes.c_size_t, vp]),
+    "jpt_layout": (ctypes.c_int32, [vp, u32, vp, vp, ctypes.c_size_t, vp]),
+    "jpt_make_level_desc": (ctypes.c_int32, [vp, u64, u64, u32, u32, u32, vp]),
+    "jpt_scan_entries": (u32, [u32]),
+    "jpt_mark_blocks": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
+    "jpt_decode_blocks": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
+    "jpt_entropy_decode": (ctypes.c_int32, [vp, vp, vp, vp]),
+    "jpt_idct_color": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
+    "jpt_resolve": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
+    "jpt_version": (u32, []),
+    "jpt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+_lib = None
+
+
+class JptError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__("%s failed: %d (%s)" % (fn, status, lib().jpt_status_string(status).decode()))
+
+
+def lib():
+    """Load libjpt.so (built in-tree by __graft_entry__.build()).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libjpt.so not built at %s: run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn, st):
+    if st != JPT_OK:
+        raise JptError(fn, st)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(vp)
+
+
+# ------------------------------------------------------------- host side
+class LevelIndex:
+    """Result of jpt_build_index for one level (host arrays)."""
+
+    def __init__(self, info: LevelInfo, stream: np.ndarray, records: np.ndarray):
+        self.info, self.stream, self.records = info, stream, records
+
+
+def build_index(jpeg: bytes) -> LevelIndex:
+    buf = np.frombuffer(jpeg, np.uint8)
+    info = LevelInfo()
+    L = lib()
+    _check("jpt_build_index", L.jpt_build_index(_np_ptr(buf), len(buf), ctypes.byref(info), None, 0, None, 0))
+    stream = np.zeros(info.stream_words, np.uint32)
+    records = np.zeros(info.n_records * RECORD_BYTES, np.uint8)
+    _check("jpt_build_index", L.jpt_build_index(_np_ptr(buf), len(buf), ctypes.byref(info), _np_ptr(stream),
+                                                len(stream), _np_ptr(records), len(records)))
+    return LevelIndex(info, stream, records)
+
+
+def build_tables(info: LevelInfo) -> np.ndarray:
+    out = np.zeros(TABLESET_WORDS, np.uint32)
+    n = ctypes.c_size_t(0)
+    _check("jpt_build_tables", lib().jpt_build_tables(ctypes.byref(info), _np_ptr(out), len(out), ctypes.byref(n)))
+    return out
+
+
+def layout(infos: list[LevelInfo]):
+    arr = (LevelInfo * len(infos))(*infos)
+    base = np.zeros(len(infos), np.uint32)
+    nb = u32(0)
+    L = lib()
+    _check("jpt_layout", L.jpt_layout(arr, len(infos), _np_ptr(base), None, 0, ctypes.byref(nb)))
+    wl = np.zeros(max(1, nb.value // 32), np.uint32)
+    _check("jpt_layout", L.jpt_layout(arr, len(infos), _np_ptr(base), _np_ptr(wl), len(wl), ctypes.byref(nb)))
+    return base, wl, nb.value
+
+
+def _table_key(info: LevelInfo) -> bytes:
+    return bytes(info.huff_bits) + bytes(info.huff_vals) + bytes(info.huff_nvals)
+
+
+class HostScene:
+    """Index build and descriptors of a texture set (no device memory)."""
+
+    def __init__(self, textures, threads: int | None = None):
+        self.textures = textures
+        jpegs, tex_first, tex_count = [], [], []
+        for t in textures:
+            tex_first.append(len(jpegs)); tex_count.append(len(t.jpegs))
+            jpegs.extend(t.jpegs)
+        threads = threads or min(16, os.cpu_count() or 1)
+        with ThreadPoolExecutor(threads) as ex:
+            self.levels = list(ex.map(build_index, jpegs))
+        self.tex_first = tex_first; self.tex_count = tex_count
+        infos = [l.info for l in self.levels]
+        self.blk_base, self.word_level, self.n_blocks = layout(infos)
+        # deduplicate Huffman table sets and quant tables by content
+        self.tablesets, ts_index, self.level_ts = [], {}, []
+        self.quants, q_index, self.level_q = [], {}, []
+        for inf in infos:
+            k = _table_key(inf)
+            if k not in ts_index:
+                ts_index[k] = len(self.tablesets); self.tablesets.append(build_tables(inf))
+            self.level_ts.append(ts_index[k])
+            qk = bytes(inf.quant)
+            if qk not in q_index:
+                q_index[qk] = len(self.quants)
+                self.quants.append(np.frombuffer(qk, np.uint16).copy())
+            self.level_q.append(q_index[qk])
+        # stream / record pools (offsets in bytes, 256-byte aligned)
+        self.stream_off, self.record_off = [], []
+        so = ro = 0
+        for l in self.levels:
+            self.stream_off.append(so); so += (l.stream.nbytes + 255) // 256 * 256
+            self.record_off.append(ro); ro += (l.records.nbytes + 255) // 256 * 256
+        self.stream_bytes, self.record_bytes = max(so, 256), max(ro, 256)
+        self.n_items_total = int(sum(l.info.blk_cols * l.info.blk_rows * (4 if l.info.sampling == 444 else 1)
+                                     for l in self.levels))
+
+    def stream_pool(self) -> np.ndarray:
+        pool = np.zeros(self.stream_bytes, np.uint8)
+        for l, o in zip(self.levels, self.stream_off):
+            pool[o:o + l.stream.nbytes] = l.stream.view(np.uint8)
+        return pool
+
+    def record_pool(self) -> np.ndarray:
+        pool = np.zeros(self.record_bytes, np.uint8)
+        for l, o in zip(self.levels, self.record_off):
+            pool[o:o + l.records.nbytes] = l.records
+        return pool
+
+    def level_descs(self, stream_base: int, record_base: int) -> bytes:
+        arr = (LevelDesc * len(self.levels))()
+        L = lib()
+        for i, l in enumerate(self.levels):
+            _check("jpt_make_level_desc", L.jpt_make_level_desc(
+                ctypes.byref(l.info), stream_base + self.stream_off[i], record_base + self.record_off[i],
+                int(self.blk_base[i]), self.level_ts[i], self.level_q[i], ctypes.byref(arr[i])))
+        return bytes(arr)
+
+    def texture_descs(self) -> bytes:
+        arr = (TextureDesc * len(self.textures))()
+        for i in range(len(self.textures)):
+            f = self.tex_first[i]
+            arr[i] = TextureDesc(f, self.tex_count[i], self.levels[f].info.width, self.levels[f].info.height)
+        return bytes(arr)
+
+    def overhead(self):
+        """(paper-accounting bpp bound, effective bpp, stored bpp) over all levels."""
+        px = sum(l.info.width * l.info.height for l in self.levels)
+        mcu_px = sum(l.info.n_mcu * (256 if l.info.sampling == 420 else 64) for l in self.levels)
+        n_mcu = sum(l.info.n_mcu for l in self.levels)
+        removed = sum(l.info.removed_dc_bits for l in self.levels)
+        per = (32 + 16 * 8) / 9 + 36
+        stored = sum(l.info.n_records * 512 + l.info.stream_bits for l in self.levels)
+        return per * n_mcu / mcu_px, (per * n_mcu - removed) / mcu_px, stored / px
+
+
+# ----------------------------------------------------------- device side
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_bytes(data: bytes | np.ndarray, device):
+    torch = _torch()
+    a = np.frombuffer(data, np.uint8) if isinstance(data, (bytes, bytearray)) else data.view(np.uint8).ravel()
+    t = torch.empty(max(len(a), 1), dtype=torch.uint8, device=device)
+    if len(a):
+        t[: len(a)].copy_(torch.from_numpy(a.copy()))
+    return t
+
+
+class DeviceScene:
+    """Compressed textures resident in HBM plus their descriptors."""
+
+    def __init__(self, host: HostScene, device="cuda"):
+        torch = _torch()
+        self.host = host
+        self.device = torch.device(device)
+        self.streams = _dev_bytes(host.stream_pool(), device)
+        self.records = _dev_bytes(host.record_pool(), device)
+        self.levels_t = _dev_bytes(host.level_descs(self.streams.data_ptr(), self.records.data_ptr()), device)
+        self.textures_t = _dev_bytes(host.texture_descs(), device)
+        self.word_level_t = _dev_bytes(host.word_level, device)
+        self.tables_t = _dev_bytes(np.concatenate(host.tablesets), device)
+        self.quant_t = _dev_bytes(np.concatenate(host.quants), device)
+        self.c = SceneC(self.levels_t.data_ptr(), self.textures_t.data_ptr(), self.word_level_t.data_ptr(),
+                        self.tables_t.data_ptr(), self.quant_t.data_ptr(), len(host.levels), len(host.textures),
+                        len(host.tablesets), len(host.quants), host.n_blocks, 0)
+        self.n_blocks = host.n_blocks
+
+    def compressed_bytes(self) -> int:
+        return sum(l.stream.nbytes + l.records.nbytes for l in self.host.levels)
+
+
+class Frame:
+    """Per-frame device scratch: visibility bitmask, work list, counters, scan, coefficients."""
+
+    def __init__(self, scene: DeviceScene, max_items: int):
+        torch = _torch()
+        d = scene.device
+        n_words = scene.n_blocks // 32
+        self.vis = torch.zeros(n_words, dtype=torch.int32, device=d)
+        self.work = torch.zeros(max(1, max_items), dtype=torch.int32, device=d)
+        self.counters = torch.zeros(N_COUNTERS, dtype=torch.int32, device=d)
+        self.scan = torch.zeros(int(lib().jpt_scan_entries(scene.n_blocks)), dtype=torch.int64, device=d)
+        self.coef = torch.zeros(max(1, max_items) * ITEM_COEFS, dtype=torch.int16, device=d)
+        self.c = FrameC(self.vis.data_ptr(), self.work.data_ptr(), self.counters.data_ptr(), self.scan.data_ptr(),
+                        self.coef.data_ptr(), max_items, 0)
+
+    def counters_host(self) -> np.ndarray:
+        return self.counters.cpu().numpy().view(np.uint32)
+
+    def work_items(self) -> np.ndarray:
+        n = int(self.counters_host()[CTR_ITEMS])
+        return self.work[:n].cpu().numpy().view(np.uint32)
+
+
+class Cache:
+    """Decoded-block cache: slots of 16x16 RGBA8 texels and the block -> slot table."""
+
+    def __init__(self, scene: DeviceScene, n_slots: int, policy: int = CACHE_NONE):
+        torch = _torch()
+        d = scene.device
+        self.texels = torch.zeros(max(1, n_slots) * 256, dtype=torch.int32, device=d)
+        self.slot_of = torch.full((scene.n_blocks,), -1, dtype=torch.int32, device=d)
+        self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), None, None, None, n_slots, policy)
+        self.n_slots = n_slots
+
+
+class Views:
+    """G-buffers and framebuffers of one or more views."""
+
+    def __init__(self, gbufs, device="cuda"):
+        torch = _torch()
+        self.gbufs, self.frames = [], []
+        arr = (ViewC * len(gbufs))()
+        for i, g in enumerate(gbufs):
+            H, W = g.shape
+            gt = torch.from_numpy(np.ascontiguousarray(g).view(np.int32).reshape(H, W, 4).copy()).to(device)
+            ft = torch.zeros((H, W), dtype=torch.int32, device=device)
+            self.gbufs.append(gt); self.frames.append(ft)
+            arr[i] = ViewC(gt.data_ptr(), ft.data_ptr(), W, H, W, W)
+        self.c = arr
+        self.n = len(gbufs)
+        self.n_pixels = sum(g.shape[0] * g.shape[1] for g in gbufs)
+
+    def frame_host(self, i=0) -> np.ndarray:
+        return self.frames[i].cpu().numpy().view(np.uint32)
+
+
+def current_stream():
+    return vp(_torch().cuda.current_stream().cuda_stream)
+
+
+def mark_blocks(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Cache | None, tuning=None,
+                stream=None):
+    _check("jpt_mark_blocks", lib().jpt_mark_blocks(
+        ctypes.byref(scene.c), views.c, views.n, filt, ctypes.byref(frame.c),
+        ctypes.byref(cache.c) if cache is not None else None, ctypes.byref(tuning) if tuning else None,
+        stream if stream is not None else current_stream()))
+
+
+def entropy_decode(scene: DeviceScene, frame: Frame, tuning=None, stream=None):
+    _check("jpt_entropy_decode", lib().jpt_entropy_decode(
+        ctypes.byref(scene.c), ctypes.byref(frame.c), ctypes.byref(tuning) if tuning else None,
+        stream if stream is not None else current_stream()))
+
+
+def decode_blocks(scene: DeviceScene, frame: Frame, cache: Cache, idct_mode: int = IDCT_MFMA_F16, tuning=None,
+                  stream=None):
+    _check("jpt_decode_blocks", lib().jpt_decode_blocks(
+        ctypes.byref(scene.c), ctypes.byref(frame.c), ctypes.byref(cache.c), idct_mode,
+        ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
+
+
+def idct_color(scene: DeviceScene, frame: Frame, cache: Cache, idct_mode: int = IDCT_MFMA_F16, tuning=None,
+               stream=None):
+    _check("jpt_idct_color", lib().jpt_idct_color(
+        ctypes.byref(scene.c), ctypes.byref(frame.c), ctypes.byref(cache.c), idct_mode,
+        ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
+
+
+def resolve(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Cache, tuning=None, stream=None):
+    _check("jpt_resolve", lib().jpt_resolve(
+        ctypes.byref(scene.c), views.c, views.n, filt, ctypes.byref(frame.c), ctypes.byref(cache.c),
+        ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
+
+
+class Renderer:
+    """One frame of the plain form: mark -> decode -> resolve on the current stream."""
+
+    def __init__(self, textures, gbufs, filt, device="cuda", max_items=None, n_slots=None, host=None):
+        self.host = host or HostScene(textures)
+        self.scene = DeviceScene(self.host, device)
+        self.views = Views(gbufs, device)
+        self.filter = filt
+        taps = 8 if filt == FILTER_TRILINEAR else (4 if filt == FILTER_BILINEAR else 1)
+        cap = self.host.n_items_total
+        self.max_items = int(max_items or min(cap, taps * 4 * self.views.n_pixels + 64))
+        self.frame = Frame(self.scene, self.max_items)
+        self.cache = Cache(self.scene, int(n_slots or min(self.host.n_blocks, self.max_items)), CACHE_NONE)
+
+    def mark(self, stream=None):
+        mark_blocks(self.scene, self.views, self.filter, self.frame, self.cache, stream=stream)
+
+    def decode(self, stream=None, idct_mode=IDCT_MFMA_F16):
+        decode_blocks(self.scene, self.frame, self.cache, idct_mode, stream=stream)
+
+    def resolve(self, stream=None):
+        resolve(self.scene, self.views, self.filter, self.frame, self.cache, stream=stream)
+
+    def render(self, stream=None):
+        self.mark(stream)
+        self.decode(stream)
+        self.resolve(stream)

@@ -1,0 +1,140 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: visible blocks, work items and coefficients bit-exact; texels within
+1 LSB of the fp64 oracle with every mismatch at a rounding near-tie; frames
+bit-exact against the oracle's resolve of the GPU texels and within 1 LSB of
+the oracle's full render.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import parity
+from paper_2510_08166_amd.synth import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def run(wl, **kw):
+    import torch
+    from paper_2510_08166_amd import jpt
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, **kw)
+    r.render()
+    torch.cuda.synchronize()
+    ctr = r.frame.counters_host()
+    items = r.frame.work_items()
+    n = len(items)
+    coef = r.frame.coef[: n * jpt.ITEM_COEFS].cpu().numpy().reshape(n, 6, 64)
+    n_new = min(int(ctr[jpt.CTR_NEW]), r.cache.n_slots)
+    tiles = r.cache.texels[: n_new * 256].cpu().numpy().view(np.uint32).reshape(n_new, 256)
+    frames = [r.views.frame_host(i) for i in range(r.views.n)]
+    return r, ctr, items, coef, tiles, frames
+
+
+def full_parity(wl, coef_sample=None, texel_sample=None, full_render=True):
+    from paper_2510_08166_amd import jpt
+    osc = oracle.Scene(wl.textures)
+    r, ctr, items, coef, tiles, frames = run(wl)
+    print("%s: items %d new %d visible %d err %x" % (wl.name, ctr[jpt.CTR_ITEMS], ctr[jpt.CTR_NEW],
+                                                     ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_ERROR]), flush=True)
+    assert ctr[jpt.CTR_ERROR] == 0
+    blocks = parity.visible_blocks(osc, wl.views, wl.filter)
+    assert ctr[jpt.CTR_NEW] == len(blocks) and ctr[jpt.CTR_VISIBLE] == len(blocks)
+    assert np.array_equal(items, parity.expected_items(osc, blocks))
+    lc = parity.LevelCache(osc)
+    assert parity.check_coefs(lc, items, coef, coef_sample) == []
+    maxd, nmis, tie, n = parity.check_texels(lc, blocks, tiles, texel_sample)
+    print("texels: max diff %d, %d of %d channels differ, worst tie distance %.2e" % (maxd, nmis, n, tie))
+    assert maxd <= 1 and tie < 0.01
+    imgs = parity.levels_from_tiles(osc, blocks, tiles)
+    for g, f in zip(wl.views, frames):
+        ref, bad = osc.resolve(g, wl.filter, imgs)
+        assert bad == 0
+        assert np.array_equal(f, ref), "frame differs from the oracle's resolve of the GPU texels"
+        if full_render:
+            full, _, _ = osc.render(g, wl.filter)
+            assert parity.frame_diff(f, full) <= 1
+    return r, osc, blocks
+
+
+def test_tiny_all_blocks(gpu):
+    wl = configs.tiny()
+    r, osc, blocks = full_parity(wl)
+    assert len(blocks) == 256                      # all 1024 luma 8x8 blocks of the 256^2 texture
+    assert len(r.frame.work_items()) * 6 == 1536   # 1536 data units
+    # nearest at texel centres: the frame is the decoded texture itself
+    lvl = osc.decode_level(0)
+    f = oracle.unpack_frame(r.views.frame_host())
+    assert np.abs(f[:, :, :3].astype(int) - lvl.astype(int)).max() <= 1
+
+
+@pytest.mark.parametrize("filt", [configs.FILTER_NEAREST, configs.FILTER_BILINEAR, configs.FILTER_TRILINEAR])
+def test_reduced_filters(gpu, filt):
+    wl = configs.reduced(seed=11, filt=filt)
+    full_parity(wl)
+
+
+def test_reduced_444_and_ragged(gpu):
+    # 4:4:4 textures with a side that is not a multiple of 16 -> partial blocks and MCUs
+    wl = configs.quad_scene(21, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444,
+                            filt=configs.FILTER_BILINEAR, name="444 ragged")
+    full_parity(wl)
+
+
+def test_many_tiles(gpu):
+    # more work items than one decode wave and several scan tiles of bitmask words
+    wl = configs.quad_scene(5, 12, 512, 40, 95, 6, 640, 360, 40, filt=configs.FILTER_BILINEAR, name="many tiles")
+    full_parity(wl, full_render=False)
+
+
+def test_background_only(gpu):
+    from paper_2510_08166_amd import jpt
+    wl = configs.tiny()
+    wl.views[0]["tex"] = 0xFFFFFFFF
+    r, ctr, items, coef, tiles, frames = run(wl)
+    assert ctr[jpt.CTR_ITEMS] == 0 and ctr[jpt.CTR_ERROR] == 0
+    assert not frames[0].any()
+
+
+def test_invalid_pixels_flagged(gpu):
+    from paper_2510_08166_amd import jpt
+    wl = configs.tiny()
+    g = wl.views[0]
+    g["u"][0, 0] = np.nan
+    g["tex"][0, 1] = 7            # no such texture
+    g["v"][0, 2] = np.float32(1e12)
+    r, ctr, items, coef, tiles, frames = run(wl)
+    assert ctr[jpt.CTR_ERROR] & jpt.ERR_PIXEL
+    assert frames[0][0, 0] == jpt.TEXEL_INVALID and frames[0][0, 1] == jpt.TEXEL_INVALID
+    assert frames[0][0, 2] == jpt.TEXEL_INVALID
+    osc = oracle.Scene(wl.textures)
+    ref, _, bad = osc.render(g, wl.filter)
+    assert bad == 3
+    assert parity.frame_diff(frames[0], ref) <= 1
+
+
+def test_capacity_overflow_is_flagged(gpu):
+    from paper_2510_08166_amd import jpt
+    wl = configs.tiny()
+    r, ctr, items, coef, tiles, frames = run(wl, max_items=100, n_slots=100)
+    assert ctr[jpt.CTR_ERROR] & jpt.ERR_CAPACITY
+    assert ctr[jpt.CTR_ITEMS] == 100
+    f = frames[0]
+    assert (f == jpt.TEXEL_INVALID).sum() > 0
+
+
+def test_corrupt_stream_flagged(gpu):
+    import torch
+    from paper_2510_08166_amd import jpt
+    wl = configs.tiny()
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter)
+    # all-ones bits are no code of the Annex K tables: every MCU must fail
+    r.scene.streams.fill_(0xFF)
+    r.render()
+    torch.cuda.synchronize()
+    ctr = r.frame.counters_host()
+    assert ctr[jpt.CTR_ERROR] & jpt.ERR_CORRUPT
+    assert ctr[jpt.CTR_ERROR_ITEM] == 0
+    items = r.frame.work_items()
+    assert (items >> 31).all()
+    assert (r.views.frame_host() == jpt.TEXEL_INVALID).all()
