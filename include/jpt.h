@@ -111,7 +111,9 @@ typedef int32_t jpt_status;
  * stored as absolute values in the records instead; the other Y DCs of a
  * 4:2:0 MCU stay coded as differences to the previous Y of the same MCU.
  * Stored as 32-bit words, bit 31 of word 0 is the first bit; followed by
- * JPT_STREAM_PAD_WORDS zero words.
+ * at least JPT_STREAM_PAD_WORDS zero words, the total rounded up to a
+ * multiple of 4 words (info.stream_words); the device address of a
+ * level's stream must be 16-byte aligned.
  *
  * Records: one 64-byte record per 9 MCUs (raster order), little-endian:
  *   bytes 0..3    u32 bit offset of MCU 9g in the spliced stream
@@ -162,7 +164,7 @@ jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level_info *info
  * tables (the paper's per-code matching loop replaced by table lookup).
  * tables_out: host, JPT_TABLESET_WORDS u32 (or NULL to query *words).
  * Errors: JPT_E_ARG, JPT_E_CORRUPT (over-full code), JPT_E_BUFSIZE. */
-#define JPT_TABLESET_WORDS 4608u
+#define JPT_TABLESET_WORDS 6656u
 jpt_status jpt_build_tables(const jpt_level_info *info, uint32_t *tables_out, size_t cap_words, size_t *words);
 
 /* Block-id layout of a scene (see "block id" above).  infos: n_levels

@@ -29,157 +29,215 @@ typedef float float16v __attribute__((ext_vector_type(16)));
 constexpr int kItemCoefs = JPT_ITEMS_DU * 64;  // int16 per work item
 
 __device__ __forceinline__ int sext12(uint32_t v) { return (int)(v << 20) >> 20; }
-__device__ __forceinline__ uint32_t rec_rel(const uint32_t *rec, uint32_t i) {
-    return (rec[1 + (i >> 1)] >> ((i & 1) * 16)) & 0xFFFFu;
-}
+// branch-free select (c is 0 or 1)
+__device__ __forceinline__ int bsel(uint32_t c, int a, int b) { return b ^ ((a ^ b) & -(int)c); }
 
 // ------------------------------------------------------------- entropy
+typedef const __attribute__((address_space(1))) uint32_t *gu32;
+
+constexpr int kWin = 48;  // words of each lane's MCU staged in LDS (1536 bits)
+
+// Codes longer than the fast-table index: canonical decoding (the first
+// length whose largest code is >= the prefix), returned in the fast-entry
+// format without the value, or JPT_FE_BAD for no code / an invalid symbol.
+__device__ __noinline__ uint32_t slow_entry(const uint32_t *tab, uint32_t tsel, uint32_t peek) {
+    const uint32_t *sl = tab + JPT_SLOW_OFFSET + tsel * JPT_SLOW_WORDS;
+    for (int c = JPT_FAST_BITS + 1; c <= 16; c++) {
+        const uint32_t code = peek >> (32 - c);
+        if ((int)code <= (int)sl[c]) {
+            const uint32_t si = (code + sl[17 + c]) & 255u;
+            const uint32_t sym = (sl[34 + (si >> 2)] >> ((si & 3) * 8)) & 0xFFu;
+            uint32_t run, size;
+            bool bad;
+            if (tsel & 1) {
+                run = sym >> 4; size = sym & 15;
+                bad = size > 10 || (size == 0 && run != 0 && run != 15);
+            } else {
+                run = 0; size = sym;
+                bad = size > 11;
+            }
+            return bad ? JPT_FE_BAD : ((uint32_t)c | (size << 6) | (run << 10));
+        }
+    }
+    return JPT_FE_BAD;
+}
+
 template <bool kLdsTables>
 __global__ __launch_bounds__(64) void k_entropy(const jpt_level_desc *__restrict__ levels,
                                                 const uint32_t *__restrict__ word_level,
                                                 const uint32_t *__restrict__ tables, uint32_t *__restrict__ work,
                                                 uint32_t *__restrict__ counters, int16_t *__restrict__ coef) {
-    __shared__ uint32_t s_tab[kLdsTables ? JPT_TABLESET_WORDS : 1];
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[kLdsTables ? JPT_TABLESET_WORDS : 4];
     __shared__ __attribute__((aligned(16))) int16_t s_coef[64 * kItemCoefs];
+    __shared__ uint32_t s_win[kWin * 64];  // word i of lane l at i*64 + l
     const uint32_t lane = threadIdx.x;
     const uint32_t n_items = counters[JPT_CTR_ITEMS];
     if (blockIdx.x * 64u >= n_items) return;
-    if (kLdsTables)
-        for (uint32_t i = lane; i < JPT_TABLESET_WORDS; i += 64) s_tab[i] = tables[i];
+    if constexpr (kLdsTables) {
+        // 18 KiB of tables: all 16-byte loads in flight before the LDS stores
+        constexpr int kVec = JPT_TABLESET_WORDS / 4 / 64;
+        static_assert(JPT_TABLESET_WORDS % 256 == 0, "table set must split into 64 lanes x uint4");
+        uint4 v[kVec];
+        const uint4 *src = reinterpret_cast<const uint4 *>(tables);
+#pragma unroll
+        for (int i = 0; i < kVec; i++) v[i] = src[i * 64 + lane];
+        uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
+#pragma unroll
+        for (int i = 0; i < kVec; i++) dst[i * 64 + lane] = v[i];
+    }
 
     for (uint32_t chunk = blockIdx.x; chunk * 64u < n_items; chunk += gridDim.x) {
         int4 *z = reinterpret_cast<int4 *>(s_coef);
         for (uint32_t i = lane; i < 64u * kItemCoefs / 8u; i += 64) z[i] = make_int4(0, 0, 0, 0);
-        __syncthreads();
         const uint32_t item = chunk * 64u + lane;
+        // ---- locate the MCU: level, record, bit span, absolute DCs
+        bool active = false;
+        uint32_t w = 0, sampling = 0, start = 0, end = 0, limit = 0, wbase = 0;
+        int dc0 = 0, dc1 = 0, dc2 = 0;
+        gu32 stream = nullptr;
+        const uint32_t *tab = kLdsTables ? s_tab : tables;
         if (item < n_items) {
-            const uint32_t w = work[item];
+            w = work[item];
             const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
             const jpt_level_desc *L = levels + word_level[b >> 5];
             const uint32_t blk_base = L->blk_base, blk_cols = L->blk_cols, mcu_cols = L->mcu_cols;
-            const uint32_t n_mcu = L->n_mcu, sampling = L->sampling;
-            const uint32_t *__restrict__ stream = reinterpret_cast<const uint32_t *>(L->stream);
-            const uint32_t *__restrict__ recs = reinterpret_cast<const uint32_t *>(L->records);
+            const uint32_t n_mcu = L->n_mcu;
+            sampling = L->sampling;
+            stream = (gu32)L->stream;
+            const gu32 recs = (gu32)L->records;
             const uint32_t stream_bits = (uint32_t)L->stream_bits;
-            const uint32_t *__restrict__ tab = kLdsTables ? s_tab : tables + (size_t)L->table_set * JPT_TABLESET_WORDS;
+            if constexpr (!kLdsTables) tab = tables + (size_t)L->table_set * JPT_TABLESET_WORDS;
             const uint32_t r = b - blk_base, by = r / blk_cols, bx = r - by * blk_cols;
-            bool present = true;
             uint32_t mcu;
+            active = true;
             if (sampling == JPT_SAMPLING_444) {
                 const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
-                present = mx < mcu_cols && my < n_mcu / mcu_cols;
+                active = mx < mcu_cols && my < n_mcu / mcu_cols;
                 mcu = my * mcu_cols + mx;
             } else {
                 mcu = by * mcu_cols + bx;
             }
-            if (present) {
+            if (active) {
                 const uint32_t g = mcu / 9, j = mcu - g * 9;
-                const uint32_t *rec = recs + (size_t)g * 16;
+                const gu32 rec = recs + (size_t)g * 16;
                 const uint32_t anchor = rec[0];
-                const uint32_t start = anchor + (j ? rec_rel(rec, j - 1) : 0u);
-                const uint32_t end = (mcu + 1 >= n_mcu) ? stream_bits : (j < 8 ? anchor + rec_rel(rec, j) : rec[16]);
+                const uint32_t rel = j ? (rec[1 + ((j - 1) >> 1)] >> (((j - 1) & 1) * 16)) & 0xFFFFu : 0u;
+                start = anchor + rel;
+                end = (mcu + 1 >= n_mcu) ? stream_bits
+                                         : (j < 8 ? anchor + ((rec[1 + (j >> 1)] >> ((j & 1) * 16)) & 0xFFFFu)
+                                                  : rec[16]);
                 const uint32_t bp = 160 + 36 * j;
                 const uint64_t dv = ((((uint64_t)rec[(bp >> 5) + 1]) << 32) | rec[bp >> 5]) >> (bp & 31);
-                const int dc0 = sext12((uint32_t)dv & 0xFFFu), dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu),
-                          dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
-                const uint32_t limit = ((stream_bits + 31) >> 5) + JPT_STREAM_PAD_WORDS;
-
-                int16_t *cf = s_coef + lane * kItemCoefs;
-                uint32_t wp = start >> 5;
-                const uint32_t sh0 = start & 31;
-                uint64_t buf = ((((uint64_t)stream[wp]) << 32) | (wp + 1 < limit ? stream[wp + 1] : 0u)) << sh0;
-                int nb = 64 - (int)sh0;
-                wp += 2;
-                uint32_t nxt = wp < limit ? stream[wp] : 0u;
-                uint32_t pos = start;
-                const int ndu = sampling == JPT_SAMPLING_444 ? 3 : 6;
-                int du = 0, k = 1, comp = 0, ypred = dc0;
-                uint32_t tsel = 1;  // AC luma
-                cf[0] = (int16_t)dc0;
-                bool ok = true, done = false;
-                for (int it = 0; it < 6 * 64 + 8; ++it) {
-                    if (nb < 32) {
-                        buf |= (uint64_t)nxt << (32 - nb);
-                        nb += 32;
-                        ++wp;
-                        nxt = wp < limit ? stream[wp] : 0u;
-                    }
-                    const uint32_t peek = (uint32_t)(buf >> 32);
-                    uint32_t e = tab[tsel * JPT_FAST_SIZE + (peek >> (32 - JPT_FAST_BITS))];
-                    uint32_t len = e & 31u;
-                    int size, run;
-                    if (len == 0) {
-                        if (e & JPT_FE_BAD) { ok = false; break; }
-                        // canonical search over code lengths 11..16
-                        const uint32_t *sl = tab + JPT_SLOW_OFFSET + tsel * JPT_SLOW_WORDS;
-                        uint32_t code = 0;
-                        for (int c = JPT_FAST_BITS + 1; c <= 16; c++) {
-                            code = peek >> (32 - c);
-                            if ((int)code <= (int)sl[c]) { len = (uint32_t)c; break; }
-                        }
-                        if (len == 0) { ok = false; break; }
-                        const uint32_t si = code + sl[17 + len];
-                        const uint32_t sym = (sl[34 + ((si >> 2) & 63)] >> ((si & 3) * 8)) & 0xFFu;
-                        if (tsel & 1) {
-                            run = (int)(sym >> 4); size = (int)(sym & 15);
-                            if (size > 10 || (size == 0 && run != 0 && run != 15)) { ok = false; break; }
-                        } else {
-                            run = 0; size = (int)sym;
-                            if (size > 11) { ok = false; break; }
-                        }
-                        e = 0;
-                    } else {
-                        size = (int)((e >> 6) & 15u);
-                        run = (int)((e >> 10) & 15u);
-                    }
-                    int value;
-                    uint32_t used;
-                    if (e & JPT_FE_FUSED) {
-                        used = len;
-                        value = (int)e >> 16;
-                    } else {
-                        const uint32_t extra = size ? ((peek << len) >> (32 - size)) : 0u;
-                        value = (size && extra < (1u << (size - 1))) ? (int)extra - (1 << size) + 1 : (int)extra;
-                        used = len + (uint32_t)size;
-                    }
-                    buf <<= used;
-                    nb -= (int)used;
-                    pos += used;
-                    if (pos > end) { ok = false; break; }
-                    if (k == 0) {  // difference DC of Y data units 1..3 (4:2:0)
-                        ypred += value;
-                        if (ypred < -32768 || ypred > 32767) { ok = false; break; }
-                        cf[du * 64] = (int16_t)ypred;
-                        k = 1;
-                    } else if (size == 0) {
-                        k = run == 15 ? k + 16 : 64;  // ZRL or EOB
-                    } else {
-                        k += run;
-                        if (k > 63) { ok = false; break; }
-                        cf[du * 64 + k] = (int16_t)value;
-                        ++k;
-                    }
-                    if (k >= 64) {
-                        if (k > 64) { ok = false; break; }
-                        if (++du >= ndu) { done = true; break; }
-                        comp = sampling == JPT_SAMPLING_444 ? du : (du < 4 ? 0 : du - 3);
-                        if (comp != 0) {
-                            cf[du * 64] = (int16_t)(comp == 1 ? dc1 : dc2);
-                            k = 1;
-                            tsel = 3;
-                        } else {
-                            k = 0;
-                            tsel = 0;
-                        }
-                    } else {
-                        tsel = (comp ? 2u : 0u) + (k != 0 ? 1u : 0u);
-                    }
-                }
-                if (!(done && ok && pos == end)) {
-                    atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CORRUPT);
-                    atomicMin(counters + JPT_CTR_ERROR_ITEM, item);
-                    work[item] = w | 0x80000000u;
-                }
+                dc0 = sext12((uint32_t)dv & 0xFFFu);
+                dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu);
+                dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
+                limit = (uint32_t)JPT_STREAM_WORDS(stream_bits);
+                wbase = (start >> 5) & ~3u;
+            }
+        }
+        // ---- stage the first kWin words of each MCU into LDS (16-byte loads, all in flight)
+        {
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            typedef const __attribute__((address_space(1))) u32x4 *gu32x4;
+            u32x4 v[kWin / 4];
+#pragma unroll
+            for (int i = 0; i < kWin / 4; i++) {
+                const uint32_t wi = wbase + 4 * i;
+                v[i] = u32x4{0u, 0u, 0u, 0u};
+                if (active && wi < limit) v[i] = *(gu32x4)(stream + wi);
+            }
+#pragma unroll
+            for (int i = 0; i < kWin / 4; i++) {
+                s_win[(4 * i + 0) * 64 + lane] = v[i].x;
+                s_win[(4 * i + 1) * 64 + lane] = v[i].y;
+                s_win[(4 * i + 2) * 64 + lane] = v[i].z;
+                s_win[(4 * i + 3) * 64 + lane] = v[i].w;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            int16_t *cf = s_coef + lane * kItemCoefs;
+            uint32_t wp = start >> 5;
+            const uint32_t sh0 = start & 31;
+            auto word_at = [&](uint32_t wi) -> uint32_t {  // the LDS window, then HBM past its end
+                const uint32_t off = wi - wbase;
+                if (off < (uint32_t)kWin) return s_win[off * 64 + lane];
+                return wi < limit ? stream[wi] : 0u;
+            };
+            uint64_t buf = ((((uint64_t)word_at(wp)) << 32) | word_at(wp + 1)) << sh0;
+            int nb = 64 - (int)sh0;  // valid bits in buf, >= 32 at the top of every iteration
+            wp += 2;
+            uint32_t pos = start;
+            const bool s444 = sampling == JPT_SAMPLING_444;
+            const int ndu = s444 ? 3 : 6;
+            uint32_t thr[4];  // start of the long-code region of each table
+#pragma unroll
+            for (int t = 0; t < 4; t++) thr[t] = tab[JPT_SLOW_OFFSET + t * JPT_SLOW_WORDS + JPT_SLOW_T];
+            // the absolute DCs from the record
+            cf[0] = (int16_t)dc0;
+            cf[(s444 ? 1 : 4) * 64] = (int16_t)dc1;
+            cf[(s444 ? 2 : 5) * 64] = (int16_t)dc2;
+            int du = 0, k = 1, ypred = dc0;
+            uint32_t toff1 = 1 * JPT_FAST_SIZE, toff2 = JPT_LONG_OFFSET + 1 * JPT_LONG_SIZE, Tcur = thr[1];
+            bool err = false, done = false;
+            // One symbol per iteration, written as straight-line code with
+            // selects; the refill word is read from LDS before it is known to
+            // be needed so that its latency overlaps the table lookups.
+            for (int it = 0; it < 6 * 64 + 8; ++it) {
+                if (done || err) break;
+                const uint32_t off = wp - wbase;
+                uint32_t wnext = s_win[min(off, (uint32_t)kWin - 1u) * 64 + lane];
+                const uint32_t peek = (uint32_t)(buf >> 32);
+                // short codes from the 10-bit table, long ones from the table over
+                // [T, 65536) of the 16-bit prefix space: both reads in flight together
+                const uint32_t p16 = peek >> 16;
+                const uint32_t li = min(p16 - Tcur, (uint32_t)JPT_LONG_SIZE - 1u);
+                const uint32_t e1 = tab[toff1 + (peek >> (32 - JPT_FAST_BITS))];
+                const uint32_t e2 = tab[toff2 + li];
+                uint32_t e = p16 >= Tcur ? e2 : e1;
+                if ((e & 31u) == 0 && !(e & JPT_FE_BAD)) e = slow_entry(tab, toff1 >> 10, peek);
+                const uint32_t len = e & 31u, size = (e >> 6) & 15u, run = (e >> 10) & 15u;
+                const uint32_t fused = (e >> 5) & 1u;
+                // appended bits (0 when size is 0) and their EXTEND
+                const uint32_t extra = (uint32_t)(((uint64_t)(peek << len) << size) >> 32);
+                const uint32_t lim = (1u << size) >> 1;
+                const int vn = (int)extra - (int)(extra < lim ? (1u << size) - 1u : 0u);
+                const int value = bsel(fused, (int)e >> 16, vn);
+                const uint32_t used = len + (fused ? 0u : size);
+                buf <<= used;
+                nb -= (int)used;
+                pos += used;
+                // state: k = next zigzag position of data unit du (0: a Y difference DC follows)
+                const uint32_t is_dc = k == 0;
+                const int kr = k + (int)run;
+                ypred += is_dc ? value : 0;
+                const uint32_t write = is_dc | (size != 0);
+                const int wpos = bsel(is_dc, 0, kr);
+                const int after_zero = bsel(run == 15, k + 16, 64);           // ZRL / EOB
+                const int nk = bsel(is_dc, 1, bsel(size != 0, kr + 1, after_zero));
+                err = (len == 0) | ((write != 0) & (wpos > 63)) | (nk > 64) | ((uint32_t)(ypred + 32768) > 65535u);
+                if (write && !err) cf[du * 64 + wpos] = (int16_t)bsel(is_dc, ypred, value);
+                const bool next_du = nk == 64;
+                du += next_du ? 1 : 0;
+                done = du >= ndu;
+                const bool chroma = s444 ? du != 0 : du >= 4;
+                k = next_du ? (chroma ? 1 : 0) : nk;
+                const uint32_t tsel = (chroma ? 2u : 0u) + (k != 0 ? 1u : 0u);
+                toff1 = tsel * JPT_FAST_SIZE;
+                toff2 = JPT_LONG_OFFSET + tsel * JPT_LONG_SIZE;
+                Tcur = (tsel & 2) ? ((tsel & 1) ? thr[3] : thr[2]) : ((tsel & 1) ? thr[1] : thr[0]);
+                // refill to >= 32 valid bits
+                const bool need = nb < 32;
+                if (need && off >= (uint32_t)kWin) wnext = wp < limit ? stream[wp] : 0u;
+                const uint64_t add = (uint64_t)wnext << ((32 - nb) & 63);
+                buf |= need ? add : 0ull;
+                nb += need ? 32 : 0;
+                wp += need ? 1u : 0u;
+            }
+            if (!(done && !err && pos == end)) {
+                atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CORRUPT);
+                atomicMin(counters + JPT_CTR_ERROR_ITEM, item);
+                work[item] = w | 0x80000000u;
             }
         }
         __syncthreads();
@@ -237,6 +295,9 @@ __device__ __forceinline__ uint32_t ycc_to_rgba(float Y, float Cb, float Cr) {
 constexpr int kIdctItems = 16;                       // items per wave iteration
 constexpr int kIdctUnits = kIdctItems * JPT_ITEMS_DU;  // 96 = 3 column tiles of 32
 
+// per-item flags gathered once per tile
+constexpr uint32_t kItem444 = 1u, kItemFailed = 2u, kItemPresent = 4u, kItemValid = 8u;
+
 __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restrict__ levels,
                                                   const uint32_t *__restrict__ word_level,
                                                   const uint16_t *__restrict__ quant, const uint32_t *__restrict__ work,
@@ -245,12 +306,17 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
                                                   const uint32_t *__restrict__ slot_of,
                                                   uint32_t *__restrict__ texels) {
     __shared__ float s_samp[kIdctUnits * 64];
+    __shared__ float s_P[64];
+    __shared__ uint32_t s_slot[kIdctItems], s_quant[kIdctItems], s_flags[kIdctItems], s_q[kIdctItems];
     const uint32_t lane = threadIdx.x;
     const uint32_t n_items = counters[JPT_CTR_ITEMS];
     if (blockIdx.x * (uint32_t)kIdctItems >= n_items) return;
     const uint32_t col = lane & 31, half = lane >> 5;
 
-    // basis operands: A[m][s] holds K[32m + col][16s + 8 half + t], t = 0..7
+    // basis operands: A[m][s] holds K[32m + col][16s + 8 half + t], t = 0..7, built
+    // from the 1-D table P[u][x] = C(u)/2 cos((2x+1) u pi / 16)
+    s_P[lane] = basis1d((int)(lane >> 3), (int)(lane & 7));
+    __syncthreads();
     half8 Khi[2][4], Klo[2][4];
 #pragma unroll
     for (int m = 0; m < 2; m++)
@@ -258,49 +324,70 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
         for (int s = 0; s < 4; s++)
 #pragma unroll
             for (int t = 0; t < 8; t++) {
-                const int i = 32 * m + (int)col;            // pixel y*8+x
-                const int n = kZigZag.nat[16 * s + 8 * half + t];  // natural v*8+u
-                const float K = basis1d(n & 7, i & 7) * basis1d(n >> 3, i >> 3);
+                const int i = 32 * m + (int)col;                     // pixel y*8+x
+                const int n = kZigZag.nat[16 * s + 8 * half + t];     // natural v*8+u
+                const float K = s_P[(n & 7) * 8 + (i & 7)] * s_P[(n >> 3) * 8 + (i >> 3)];
                 const _Float16 hi = (_Float16)K;
                 Khi[m][s][t] = hi;
                 Klo[m][s][t] = (_Float16)((K - (float)hi) * 2048.0f);
             }
 
     for (uint32_t base = blockIdx.x * kIdctItems; base < n_items; base += gridDim.x * kIdctItems) {
+        // ---- item metadata, one lane per item
+        if (lane < (uint32_t)kIdctItems) {
+            const uint32_t it = base + lane;
+            uint32_t flags = 0, slot = JPT_SLOT_NONE, qi = 0, q = 0;
+            if (it < n_items) {
+                const uint32_t w = work[it];
+                const uint32_t b = (w & 0x7FFFFFFFu) >> 2;
+                q = w & 3u;
+                const jpt_level_desc *L = levels + word_level[b >> 5];
+                slot = slot_of[b];
+                qi = L->quant;
+                flags = kItemValid | ((w >> 31) ? kItemFailed : 0u);
+                if (L->sampling == JPT_SAMPLING_444) {
+                    flags |= kItem444;
+                    const uint32_t r = b - L->blk_base, by = r / L->blk_cols, bx = r - by * L->blk_cols;
+                    const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
+                    if (mx < L->mcu_cols && my < L->n_mcu / L->mcu_cols) flags |= kItemPresent;
+                } else {
+                    flags |= kItemPresent;
+                }
+            }
+            s_slot[lane] = slot; s_quant[lane] = qi; s_flags[lane] = flags; s_q[lane] = q;
+        }
+        __syncthreads();
 #pragma unroll
         for (int ct = 0; ct < kIdctUnits / 32; ct++) {
             const uint32_t d = 32 * ct + col;
-            const uint32_t it = base + d / JPT_ITEMS_DU, du = d % JPT_ITEMS_DU;
+            const uint32_t li = d / JPT_ITEMS_DU, du = d % JPT_ITEMS_DU;
+            const uint32_t flags = s_flags[li];
             int fv[4][8];
             bool wide = false;
 #pragma unroll
             for (int s = 0; s < 4; s++)
 #pragma unroll
                 for (int t = 0; t < 8; t++) fv[s][t] = 0;
-            if (it < n_items) {
-                const uint32_t b = (work[it] & 0x7FFFFFFFu) >> 2;
-                const jpt_level_desc *L = levels + word_level[b >> 5];
-                const bool s444 = L->sampling == JPT_SAMPLING_444;
-                if (!(s444 && du >= 3)) {
-                    const int comp = s444 ? (int)du : (du < 4 ? 0 : 1);
-                    const uint16_t *qt = quant + (size_t)L->quant * 128 + (comp ? 64 : 0);
-                    const int16_t *cp = coef + (size_t)it * kItemCoefs + du * 64;
+            const bool s444 = flags & kItem444;
+            if ((flags & kItemValid) && !(s444 && du >= 3)) {
+                const int comp = s444 ? (int)du : (du < 4 ? 0 : 1);
+                const uint16_t *qt = quant + (size_t)s_quant[li] * 128 + (comp ? 64 : 0);
+                const int16_t *cp = coef + (size_t)(base + li) * kItemCoefs + du * 64;
 #pragma unroll
-                    for (int s = 0; s < 4; s++) {
-                        const int4 cv = *reinterpret_cast<const int4 *>(cp + 16 * s + 8 * half);
-                        const uint4 qv = *reinterpret_cast<const uint4 *>(qt + 16 * s + 8 * half);
-                        const int32_t cw[4] = {cv.x, cv.y, cv.z, cv.w};
-                        const uint32_t qw[4] = {qv.x, qv.y, qv.z, qv.w};
+                for (int s = 0; s < 4; s++) {
+                    const int4 cv = *reinterpret_cast<const int4 *>(cp + 16 * s + 8 * half);
+                    const uint4 qv = *reinterpret_cast<const uint4 *>(qt + 16 * s + 8 * half);
+                    const int32_t cw[4] = {cv.x, cv.y, cv.z, cv.w};
+                    const uint32_t qw[4] = {qv.x, qv.y, qv.z, qv.w};
 #pragma unroll
-                        for (int p = 0; p < 4; p++) {
-                            const int c0 = (int)(int16_t)(cw[p] & 0xFFFF), c1 = cw[p] >> 16;
-                            const int q0 = (int)(qw[p] & 0xFFFFu), q1 = (int)(qw[p] >> 16);
-                            fv[s][2 * p] = c0 * q0;
-                            fv[s][2 * p + 1] = c1 * q1;
-                        }
-#pragma unroll
-                        for (int t = 0; t < 8; t++) wide |= (fv[s][t] > 2048 || fv[s][t] < -2048);
+                    for (int p = 0; p < 4; p++) {
+                        const int c0 = (int)(int16_t)(cw[p] & 0xFFFF), c1 = cw[p] >> 16;
+                        const int q0 = (int)(qw[p] & 0xFFFFu), q1 = (int)(qw[p] >> 16);
+                        fv[s][2 * p] = c0 * q0;
+                        fv[s][2 * p + 1] = c1 * q1;
                     }
+#pragma unroll
+                    for (int t = 0; t < 8; t++) wide |= (fv[s][t] > 2048 || fv[s][t] < -2048);
                 }
             }
             const bool any_wide = __ballot(wide) != 0;
@@ -348,17 +435,13 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
         __syncthreads();
         // colour conversion and store, one item at a time (1 KiB per 4:2:0 item)
         for (int li = 0; li < kIdctItems; li++) {
-            const uint32_t it = base + li;
-            if (it >= n_items) break;
-            const uint32_t w = work[it];
-            const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
-            const bool failed = (w >> 31) != 0;
-            const uint32_t slot = slot_of[b];
-            if (slot == JPT_SLOT_NONE) continue;
-            const jpt_level_desc *L = levels + word_level[b >> 5];
+            const uint32_t flags = s_flags[li], slot = s_slot[li];
+            if (!(flags & kItemValid)) break;
+            if (slot == JPT_SLOT_NONE || !(flags & kItemPresent)) continue;
+            const bool failed = flags & kItemFailed;
             const float *sp = s_samp + li * JPT_ITEMS_DU * 64;
             uint32_t *dst = texels + (size_t)slot * 256;
-            if (L->sampling != JPT_SAMPLING_444) {
+            if (!(flags & kItem444)) {
                 const uint32_t ty = lane >> 2, tx0 = (lane & 3) * 4;
                 uint32_t o[4];
 #pragma unroll
@@ -371,19 +454,16 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
                 }
                 *reinterpret_cast<uint4 *>(dst + ty * 16 + tx0) = make_uint4(o[0], o[1], o[2], o[3]);
             } else if (lane < 16) {
-                const uint32_t r = b - L->blk_base, by = r / L->blk_cols, bx = r - by * L->blk_cols;
-                const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
-                if (mx < L->mcu_cols && my < L->n_mcu / L->mcu_cols) {
-                    const uint32_t ty = lane >> 1, tx0 = (lane & 1) * 4;
-                    uint32_t o[4];
+                const uint32_t q = s_q[li];
+                const uint32_t ty = lane >> 1, tx0 = (lane & 1) * 4;
+                uint32_t o[4];
 #pragma unroll
-                    for (int i = 0; i < 4; i++) {
-                        const uint32_t p = ty * 8 + tx0 + i;
-                        o[i] = failed ? JPT_TEXEL_INVALID : ycc_to_rgba(sp[p], sp[64 + p], sp[128 + p]);
-                    }
-                    *reinterpret_cast<uint4 *>(dst + (8 * (q >> 1) + ty) * 16 + 8 * (q & 1) + tx0) =
-                        make_uint4(o[0], o[1], o[2], o[3]);
+                for (int i = 0; i < 4; i++) {
+                    const uint32_t p = ty * 8 + tx0 + i;
+                    o[i] = failed ? JPT_TEXEL_INVALID : ycc_to_rgba(sp[p], sp[64 + p], sp[128 + p]);
                 }
+                *reinterpret_cast<uint4 *>(dst + (8 * (q >> 1) + ty) * 16 + 8 * (q & 1) + tx0) =
+                    make_uint4(o[0], o[1], o[2], o[3]);
             }
         }
         __syncthreads();

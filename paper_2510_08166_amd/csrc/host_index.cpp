@@ -319,7 +319,7 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
     I.stream_bits = ww.nbits;
     I.scan_bits = scan_end;
     I.removed_dc_bits = removed;
-    I.stream_words = (uint32_t)((ww.nbits + 31) / 32 + JPT_STREAM_PAD_WORDS);
+    I.stream_words = (uint32_t)JPT_STREAM_WORDS(ww.nbits);
 
     // offsets relative to each group anchor must fit 16 bits
     for (uint32_t g = 0; g < I.n_records; g++)
@@ -409,7 +409,7 @@ extern "C" jpt_status jpt_build_tables(const jpt_level_info *info, uint32_t *out
                     fast[idx] = e;
                 }
             }
-        // slow path data (codes longer than FAST bits): per length l, the
+        // canonical data (codes longer than FAST bits): per length l, the
         // largest code (-1 if none) and the offset symbol index - code
         for (int l = 0; l <= 16; l++) {
             int32_t maxc = (l >= 1 && C.count[l]) ? C.first[l] + C.count[l] - 1 : -1;
@@ -418,7 +418,29 @@ extern "C" jpt_status jpt_build_tables(const jpt_level_info *info, uint32_t *out
         }
         uint8_t *vb = reinterpret_cast<uint8_t *>(slow + 34);
         for (int i = 0; i < 256; i++) vb[i] = C.vals[i];
-        // symbol validity of long codes is checked on use (size ranges)
+        // long table: the codes of 11..16 bits occupy [T, 65536) of the
+        // 16-bit prefix space, T = first code value after the 10-bit codes
+        const uint32_t T = (uint32_t)(C.first[JPT_FAST_BITS] + C.count[JPT_FAST_BITS]) << (16 - JPT_FAST_BITS);
+        slow[JPT_SLOW_T] = T;
+        slow[JPT_SLOW_LONG_OK] = 0;
+        if (T <= 65536u && 65536u - T <= (uint32_t)JPT_LONG_SIZE) {
+            uint32_t *lt = out + JPT_LONG_OFFSET + t * JPT_LONG_SIZE;
+            for (uint32_t i = 0; i < JPT_LONG_SIZE; i++) lt[i] = JPT_FE_BAD;  // prefixes of no code
+            for (int l = JPT_FAST_BITS + 1; l <= 16; l++)
+                for (int i = 0; i < C.count[l]; i++) {
+                    const uint32_t code = (uint32_t)(C.first[l] + i);
+                    const int sym = C.vals[C.sym_base[l] + i];
+                    const int run = is_ac ? sym >> 4 : 0, size = is_ac ? sym & 15 : sym;
+                    const bool bad = is_ac ? (size > 10 || (size == 0 && run != 0 && run != 15)) : size > 11;
+                    const uint32_t e = bad ? JPT_FE_BAD : ((uint32_t)l | ((uint32_t)size << 6) | ((uint32_t)run << 10));
+                    const int rest = 16 - l;
+                    for (uint32_t tail = 0; tail < (1u << rest); tail++) {
+                        const uint32_t p16 = (code << rest) | tail;
+                        if (p16 >= T && p16 - T < (uint32_t)JPT_LONG_SIZE) lt[p16 - T] = e;
+                    }
+                }
+            slow[JPT_SLOW_LONG_OK] = 1;
+        }
     }
     return JPT_OK;
 }

@@ -2,23 +2,37 @@
 #pragma once
 #include <stdint.h>
 
-// GPU decode tables (one table set = JPT_TABLESET_WORDS u32):
-//   [t*1024, t*1024+1024)  fast table of table t (0 DC luma, 1 AC luma,
-//                          2 DC chroma, 3 AC chroma), indexed by the next
-//                          JPT_FAST_BITS stream bits;
-//   [4096 + t*128, +128)   slow-path data of table t for longer codes:
+// GPU decode tables (one table set = JPT_TABLESET_WORDS u32), for table t
+// (0 DC luma, 1 AC luma, 2 DC chroma, 3 AC chroma):
+//   [t*1024, +1024)        fast table indexed by the next JPT_FAST_BITS bits;
+//   [4096 + t*512, +512)   long table: canonical codes longer than
+//                          JPT_FAST_BITS bits fill the top of the 16-bit code
+//                          space, [T, 65536) with T = (first code value past
+//                          the 10-bit codes) << 6; entry p16 - T for a 16-bit
+//                          prefix p16 >= T (when 65536 - T <= 512);
+//   [6144 + t*128, +128)   canonical data for the general case:
 //                          [0..16] largest code of each length (-1 if none),
 //                          [17..33] symbol index minus code per length,
-//                          [34..97] the 256 symbol bytes.
-// Fast entry: bits 0-4 bits consumed (0: take the slow path), bit 5 value
-// included (code and appended bits both fit the index), bits 6-9 size
-// (SSSS), bits 10-13 run (RRRR), bit 15 invalid symbol, bits 16-31 value.
+//                          [34..97] the 256 symbol bytes, [98] T,
+//                          [99] 1 if the long table covers [T, 65536).
+// Entry: bits 0-4 bits consumed (0: not resolved by this table), bit 5
+// value included (code and appended bits both fit the index), bits 6-9
+// size (SSSS), bits 10-13 run (RRRR), bit 15 invalid symbol, bits 16-31
+// value.
 #define JPT_FAST_BITS 10
 #define JPT_FAST_SIZE 1024
-#define JPT_SLOW_OFFSET 4096
+#define JPT_LONG_OFFSET 4096
+#define JPT_LONG_SIZE 512
+#define JPT_SLOW_OFFSET 6144
 #define JPT_SLOW_WORDS 128
+#define JPT_SLOW_T 98
+#define JPT_SLOW_LONG_OK 99
 #define JPT_FE_FUSED (1u << 5)
 #define JPT_FE_BAD (1u << 15)
 
-// Compaction: bitmask words per scan tile (256 threads x 4 words).
-#define JPT_SCAN_TILE_WORDS 1024
+// Compaction: bitmask words per scan tile (256 threads, one word each).
+#define JPT_SCAN_TILE_WORDS 256
+
+// Words of a level's spliced stream as stored: the data, at least
+// JPT_STREAM_PAD_WORDS zero words, rounded up to whole 16-byte vectors.
+#define JPT_STREAM_WORDS(bits) (((((uint64_t)(bits) + 31) / 32 + JPT_STREAM_PAD_WORDS) + 3) & ~(uint64_t)3)

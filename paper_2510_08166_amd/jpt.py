@@ -32,7 +32,7 @@ SLOT_NONE = 0xFFFFFFFF
 TEXEL_INVALID = 0xFFFF00FF
 ITEM_COEFS = 6 * 64
 RECORD_BYTES = 64
-TABLESET_WORDS = 4608
+TABLESET_WORDS = 6656
 
 
 class LevelInfo(ctypes.Structure):

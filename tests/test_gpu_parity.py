@@ -138,3 +138,29 @@ def test_corrupt_stream_flagged(gpu):
     items = r.frame.work_items()
     assert (items >> 31).all()
     assert (r.views.frame_host() == jpt.TEXEL_INVALID).all()
+
+
+def test_pil_files_with_optimised_tables(gpu):
+    """Files written by libjpeg (through PIL) with per-image optimised Huffman
+    tables: several table sets (decode tables read from HBM) and codes longer
+    than the fast-table index."""
+    import io
+    from PIL import Image
+    from paper_2510_08166_amd import synth
+    texs = []
+    for i, (q, sub) in enumerate([(92, 2), (60, 2), (85, 0), (97, 2)]):
+        rgb = synth.texture(300 + i, 192, 160)
+        levels = synth.mip_chain(rgb, 3)
+        jp = []
+        for l in levels:
+            b = io.BytesIO()
+            Image.fromarray(l).save(b, format="JPEG", quality=q, subsampling=sub, optimize=True)
+            jp.append(b.getvalue())
+        texs.append(synth.EncodedTexture(i, 192, 160, q, 420 if sub == 2 else 444, jp))
+    rng = np.random.default_rng(8)
+    quads = synth.random_quads(rng, 240, 180, 20, list(range(4)), {i: (192.0, 160.0) for i in range(4)})
+    g = synth.rasterise(240, 180, quads)
+    wl = configs.Workload("pil optimised", texs, [g], configs.FILTER_TRILINEAR)
+    from paper_2510_08166_amd import jpt
+    assert len(jpt.HostScene(texs).tablesets) > 1
+    full_parity(wl)
