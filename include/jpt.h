@@ -242,15 +242,32 @@ typedef struct jpt_frame {        /* per-frame device scratch, caller-allocated 
     uint32_t frame_no;            /* LRU timestamp of this frame */
 } jpt_frame;
 
-typedef struct jpt_cache {        /* decoded-block cache, caller-allocated */
+/* Decoded-block cache (paper: "Texture Block Cache", "Update Cache"),
+ * caller-allocated.  JPT_CACHE_NONE needs texels and slot_of only; the
+ * LRU policy also needs the other arrays and jpt_cache_reset before its
+ * first frame.  LRU policy, per frame f with visible set V and resident
+ * set R: visible resident blocks get last_used = f; the new blocks V - R
+ * take free slots; if too few are free, the resident blocks outside V with
+ * the largest age min(f - last_used, JPT_LRU_MAX_AGE) are evicted first,
+ * equal ages by the smaller block id. */
+#define JPT_LRU_MAX_AGE 1023u
+#define JPT_CACHE_META_WORDS (16u + JPT_LRU_MAX_AGE + 1u)
+typedef struct jpt_cache {
     uint32_t *texels;             /* n_slots * 256 RGBA8 texels, slot-major, 16x16 row-major */
     uint32_t *slot_of;            /* n_blocks: slot of each block (valid while resident) */
     uint32_t *owner;              /* n_slots: block in each slot or JPT_SLOT_NONE (LRU) */
     uint32_t *last_used;          /* n_slots: frame_no of last use (LRU) */
     uint32_t *resident;           /* n_blocks/32 words: resident blocks (LRU) */
+    uint32_t *free_stack;         /* n_slots: free slots, top of stack in meta (LRU) */
+    uint32_t *meta;               /* JPT_CACHE_META_WORDS: stack top, eviction plan, age histogram (LRU) */
+    uint32_t *tie_mask;           /* n_blocks/32 words: scratch of the eviction (LRU) */
     uint32_t n_slots;
     uint32_t policy;              /* JPT_CACHE_NONE / JPT_CACHE_LRU */
 } jpt_cache;
+
+/* Empty an LRU cache: every slot free, no block resident.  Device call on
+ * `stream`.  Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, void *stream);
 
 typedef struct jpt_tuning {       /* launch knobs; NULL = defaults */
     uint32_t decode_groups;       /* persistent workgroups of the decode kernels (0 = auto) */
@@ -258,7 +275,8 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults */
     uint32_t reserved[6];
 } jpt_tuning;
 
-/* Entries of jpt_frame.scan for a scene of n_blocks block ids. */
+/* Entries of jpt_frame.scan for a scene of n_blocks block ids (two scans
+ * of the block bitmask per frame). */
 uint32_t jpt_scan_entries(uint32_t n_blocks);
 
 /* ------------------------------------------------------------------ *
@@ -272,9 +290,10 @@ uint32_t jpt_scan_entries(uint32_t n_blocks);
  * ascending block-id order and assigns their cache slots:
  *   JPT_CACHE_NONE: slot = rank of the block among this frame's new blocks
  *     (blocks beyond n_slots get JPT_SLOT_NONE and raise JPT_ERR_CAPACITY);
- *   JPT_CACHE_LRU: visible resident blocks get last_used = frame_no; new
- *     blocks take free slots, else evict the resident blocks not visible this
- *     frame with the smallest (last_used, block id).
+ *   JPT_CACHE_LRU: the policy stated at jpt_cache (frame_no is the frame
+ *     index f; new blocks that find no slot get JPT_SLOT_NONE and raise
+ *     JPT_ERR_CAPACITY).  counters[JPT_CTR_EVICTED] and
+ *     [JPT_CTR_RESIDENT] report the update.
  * cache may be NULL only if nothing reads slots (block lists only).
  * Errors: JPT_E_ARG (NULL/short buffers, filter, view sizes), JPT_E_HIP. */
 jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
@@ -309,6 +328,48 @@ jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *c
  * Errors: JPT_E_ARG, JPT_E_HIP. */
 jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                        const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+/* ------------------------------------------------------------------ *
+ * Differentiable form.  The frame as a function of the dequantised DCT
+ * coefficients of this frame's work items (paper: Decode, whose stages are
+ * dequantisation, the 8x8 IDCT and the colour transform, followed by the
+ * filtered lookup of Resolve), with the rounding and clamping of the 8-bit
+ * path removed:
+ *   texel = M (IDCT(F) + (128, 0, 0)), chroma replicated over 2x2 (4:2:0),
+ *   M the JFIF full-range inverse (R = Y + 1.402 Cr, G = Y - 0.344136 Cb
+ *   - 0.714136 Cr, B = Y + 1.772 Cb);
+ *   frame = sum over the filter taps of (tap weight / 65536) x (level
+ *   weight / 256) x texel, with the integer weights of jpt_resolve held
+ *   constant.
+ * Requires every block the views read to be a work item of the last
+ * jpt_mark_blocks (JPT_CACHE_NONE with n_slots >= the visible blocks).
+ * F and dF: max_items x 6 x 64 floats, natural order (index v*8+u, v the
+ * vertical frequency), one 64-entry unit per data unit of the item (4:2:0:
+ * Y0..Y3, Cb, Cr; 4:4:4: Y, Cb, Cr, then three zero units).
+ * texel_f: n_slots x 16 x 16 x 3 floats.  frame_f / dframe: the views'
+ * pixels in order, width x height x 3 floats each, packed.  All pointers
+ * are device memory owned by the caller; calls are asynchronous on `stream`.
+ * ------------------------------------------------------------------ */
+
+/* F = coefficient x quantiser for the listed work items (from frame->coef).
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_dequantize(const jpt_scene *scene, const jpt_frame *frame, float *F, void *stream);
+
+/* Forward: F -> texel_f (the work items' texels) -> frame_f.  Invalid
+ * pixels and taps in blocks without a slot raise JPT_ERR_PIXEL in
+ * frame->counters; background pixels get 0.
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                         const jpt_frame *frame, const jpt_cache *cache, const float *F, float *texel_f,
+                         float *frame_f, void *stream);
+
+/* Backward: dframe = dL/dframe_f -> dF = dL/dF.  dtexel is scratch of
+ * n_slots x 768 int64 (texel gradients in fixed point, 2^-32 units, summed
+ * with integer atomics so that the result does not depend on their order).
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                        const jpt_frame *frame, const jpt_cache *cache, const float *dframe, int64_t *dtexel,
+                        float *dF, void *stream);
 
 uint32_t jpt_version(void);
 const char *jpt_status_string(jpt_status s);

@@ -70,6 +70,8 @@ def lib():
             L.orc_mark.argtypes = [i32, vp, vp, vp, vp, vp, vp, i64, i32, vp]
             L.orc_resolve.restype = i64
             L.orc_resolve.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp, vp]
+            L.orc_taps.restype = i64
+            L.orc_taps.argtypes = [i32, vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
             _lib = L
     return _lib
 
@@ -200,6 +202,15 @@ class Scene:
                              _p(self.lev_h), _p(self.blk_base), _p(g), g.size, filt, _p(vis))
         return np.nonzero(vis)[0].astype(np.uint32), int(bad)
 
+    def taps(self, g: np.ndarray, filt: int):
+        """Per pixel up to 8 taps: (level, x, y, weight) arrays of shape g.shape + (8,)."""
+        g = np.ascontiguousarray(g)
+        lv = np.zeros(g.shape + (8,), np.int32); x = np.zeros_like(lv); y = np.zeros_like(lv)
+        w = np.zeros(g.shape + (8,), np.float64)
+        bad = lib().orc_taps(len(self.textures), _p(self.tex_first), _p(self.tex_count), _p(self.lev_w),
+                             _p(self.lev_h), _p(g), g.size, filt, _p(lv), _p(x), _p(y), _p(w))
+        return lv, x, y, w, int(bad)
+
     def levels_of_blocks(self, blocks) -> set:
         return {self.level_of_block(int(b)) for b in blocks}
 
@@ -245,11 +256,13 @@ class LruSim:
         new   = V - R                      (to decode)
         touch = V & R                      (last_used := f)
         if |new| > free: evict the |new| - free resident blocks not in V with
-        the smallest (last_used, block id);
+        the largest age min(f - last_used, max_age), equal ages by the
+        smaller block id;
         R := (R - evicted) | new,  last_used[new] := f."""
 
-    def __init__(self, capacity: int):
+    def __init__(self, capacity: int, max_age: int = 1023):
         self.capacity = capacity
+        self.max_age = max_age
         self.last_used: dict[int, int] = {}
 
     def step(self, frame_no: int, visible) -> tuple[list, list]:
@@ -261,7 +274,7 @@ class LruSim:
         free = self.capacity - len(R)
         evicted = []
         if len(new) > free:
-            cand = sorted((self.last_used[b], b) for b in R - V)
+            cand = sorted((-min(frame_no - self.last_used[b], self.max_age), b) for b in R - V)
             need = len(new) - free
             if need > len(cand):
                 raise OracleError("visible set exceeds the cache capacity")

@@ -597,3 +597,25 @@ int64_t orc_resolve(int n_tex, const int32_t *tex_first, const int32_t *tex_coun
     }
     return bad;
 }
+
+int64_t orc_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_count, const int32_t *lev_w,
+                 const int32_t *lev_h, const orc_gpixel *g, int64_t n_px, int filter, int32_t *level, int32_t *x,
+                 int32_t *y, double *w) {
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n_px; i++) {
+        for (int k = 0; k < 8; k++) {
+            level[8 * i + k] = -1; x[8 * i + k] = 0; y[8 * i + k] = 0; w[8 * i + k] = 0.0;
+        }
+        if (g[i].tex == 0xFFFFFFFFu) continue;
+        tap_t taps[8]; int l0, l1, tw;
+        int n = pixel_taps(n_tex, tex_first, tex_count, lev_w, lev_h, &g[i], filter, taps, &l0, &l1, &tw);
+        if (n < 0) { bad++; continue; }
+        for (int k = 0; k < n; k++) {
+            level[8 * i + k] = taps[k].level;
+            x[8 * i + k] = (int32_t)taps[k].x;
+            y[8 * i + k] = (int32_t)taps[k].y;
+            w[8 * i + k] = ((double)taps[k].w / 65536.0) * ((double)taps[k].lw / 256.0);
+        }
+    }
+    return bad;
+}

@@ -129,6 +129,14 @@ int64_t orc_resolve(int n_tex, const int32_t *tex_first, const int32_t *tex_coun
                     const int32_t *lev_h, const uint8_t *const *level_rgb, const double *const *level_f64,
                     const orc_gpixel *g, int64_t n_px, int filter, uint32_t *frame, double *frame_f64);
 
+/* The taps of every pixel as the resolve uses them (at most 8 per pixel):
+ * level, texel x, y and weight (tap weight / 65536 times level weight / 256;
+ * unused taps have level -1 and weight 0).  Returns the number of invalid
+ * pixels. */
+int64_t orc_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_count, const int32_t *lev_w,
+                 const int32_t *lev_h, const orc_gpixel *g, int64_t n_px, int filter, int32_t *level, int32_t *x,
+                 int32_t *y, double *w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,17 +48,55 @@ JPT_DEV bool axis(float u, uint32_t n, bool linear, uint32_t &x0, uint32_t &x1, 
     return true;
 }
 
+// Sampling view of the scene descriptors: texture -> (first level, level
+// count); level -> (width, height, first block id, blocks per row).
+struct TexRec { uint32_t first, n; };
+struct LevRec { uint32_t w, h, blk_base, blk_cols; };
+
+// Descriptors read from HBM.
+struct GlobalDesc {
+    const jpt_level_desc *__restrict__ levels;
+    const jpt_texture_desc *__restrict__ texs;
+    JPT_DEV TexRec tex(uint32_t t) const { return TexRec{texs[t].first_level, texs[t].n_levels}; }
+    JPT_DEV LevRec lev(uint32_t l) const {
+        const jpt_level_desc *d = levels + l;
+        return LevRec{d->width, d->height, d->blk_base, d->blk_cols};
+    }
+};
+
+// Descriptors copied into LDS by the workgroup (small scenes).
+struct LdsDesc {
+    const TexRec *t;
+    const LevRec *l;
+    JPT_DEV TexRec tex(uint32_t i) const { return t[i]; }
+    JPT_DEV LevRec lev(uint32_t i) const { return l[i]; }
+};
+
+// LDS capacity of the descriptor cache of mark and resolve.
+constexpr uint32_t kLdsTexCap = 512, kLdsLevCap = 1024;
+
+// Copy the descriptors into LDS (all threads of the block take part; the
+// caller synchronises).
+JPT_DEV void load_desc_lds(const jpt_level_desc *__restrict__ levels, const jpt_texture_desc *__restrict__ texs,
+                           uint32_t n_tex, uint32_t n_lev, TexRec *s_t, LevRec *s_l) {
+    for (uint32_t i = threadIdx.x; i < n_tex; i += blockDim.x) s_t[i] = TexRec{texs[i].first_level, texs[i].n_levels};
+    for (uint32_t i = threadIdx.x; i < n_lev; i += blockDim.x) {
+        const jpt_level_desc *d = levels + i;
+        s_l[i] = LevRec{d->width, d->height, d->blk_base, d->blk_cols};
+    }
+}
+
 // Levels and footprints of a pixel (up to two levels).  Returns PIX_*.
-JPT_DEV int pixel_footprint(const jpt_level_desc *__restrict__ levels, const jpt_texture_desc *__restrict__ texs,
-                            uint32_t n_tex, const jpt_gpixel &px, uint32_t filter, LevelFoot foot[2], int &nfoot,
-                            uint32_t &tw) {
+template <class Desc>
+JPT_DEV int pixel_footprint(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter, LevelFoot foot[2],
+                            int &nfoot, uint32_t &tw) {
     nfoot = 0;
     tw = 0;
     if (px.tex == JPT_TEX_BACKGROUND) return PIX_BACKGROUND;
     if (px.tex >= n_tex) return PIX_INVALID;
     if (!isfinite(px.u) || !isfinite(px.v) || !isfinite(px.lod)) return PIX_INVALID;
-    const jpt_texture_desc td = texs[px.tex];
-    const int L = (int)td.n_levels;
+    const TexRec td = D.tex(px.tex);
+    const int L = (int)td.n;
     if (L <= 0) return PIX_INVALID;
     int lv[2];
     uint32_t lw[2];
@@ -91,12 +129,11 @@ JPT_DEV int pixel_footprint(const jpt_level_desc *__restrict__ levels, const jpt
     for (int k = 0; k < 2; k++) {
         if (k >= nl) break;
         LevelFoot &F = foot[k];
-        const jpt_level_desc *ld = levels + td.first_level + lv[k];
-        const uint32_t w = ld->width, h = ld->height;
-        F.blk_base = ld->blk_base;
-        F.blk_cols = ld->blk_cols;
+        const LevRec lr = D.lev(td.first + lv[k]);
+        F.blk_base = lr.blk_base;
+        F.blk_cols = lr.blk_cols;
         F.lw = lw[k];
-        if (!axis(px.u, w, linear, F.x0, F.x1, F.fx) || !axis(px.v, h, linear, F.y0, F.y1, F.fy))
+        if (!axis(px.u, lr.w, linear, F.x0, F.x1, F.fx) || !axis(px.v, lr.h, linear, F.y0, F.y1, F.fy))
             return PIX_INVALID;
     }
     nfoot = nl;

@@ -489,7 +489,7 @@ extern "C" jpt_status jpt_make_level_desc(const jpt_level_info *info, uint64_t s
 
 extern "C" uint32_t jpt_scan_entries(uint32_t n_blocks) {
     uint32_t words = (n_blocks + 31) / 32;
-    return (words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS + 1;
+    return 2 * ((words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS) + 2;
 }
 
 extern "C" uint32_t jpt_version(void) { return JPT_ABI_VERSION; }

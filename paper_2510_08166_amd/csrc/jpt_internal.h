@@ -36,3 +36,12 @@
 // Words of a level's spliced stream as stored: the data, at least
 // JPT_STREAM_PAD_WORDS zero words, rounded up to whole 16-byte vectors.
 #define JPT_STREAM_WORDS(bits) (((((uint64_t)(bits) + 31) / 32 + JPT_STREAM_PAD_WORDS) + 3) & ~(uint64_t)3)
+
+// LRU cache metadata (jpt_cache.meta): scalars, then the age histogram.
+#define JPT_META_TOP 0        // free slots on the stack
+#define JPT_META_NEW 1        // blocks to place this frame
+#define JPT_META_NEED 2       // evictions needed this frame
+#define JPT_META_ABIN 3       // age bin of the last evicted blocks
+#define JPT_META_TIES 4       // blocks of that bin to evict (smallest ids)
+#define JPT_META_EVICTED 5    // evicted this frame
+#define JPT_META_HIST 16      // JPT_LRU_MAX_AGE + 1 bins

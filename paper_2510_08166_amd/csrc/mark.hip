@@ -43,50 +43,60 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
     atomicOr(vis + word, bit);  // set crowded: go straight to HBM
 }
 
+template <bool kLdsDesc>
 __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
-                                                       const jpt_gpixel *__restrict__ gbuf, uint32_t W, uint32_t H,
-                                                       uint32_t pitch, uint32_t filter, uint32_t *__restrict__ vis,
-                                                       uint32_t *__restrict__ counters) {
+                                                       uint32_t n_lev, const jpt_gpixel *__restrict__ gbuf,
+                                                       uint32_t W, uint32_t H, uint32_t pitch, uint32_t filter,
+                                                       uint32_t *__restrict__ vis, uint32_t *__restrict__ counters) {
+    constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize];
+    __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
+    __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
     __shared__ uint32_t s_bad;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t x = blockIdx.x * kTileW + lane;
+    // all of this lane's G-buffer pixels in flight at once (rows wv, wv+4, ...)
+    jpt_gpixel px[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+        const uint32_t y = blockIdx.y * kTileH + wv + r * (kMarkThreads / 64);
+        px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+    }
     for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
         s_key[i] = 0xFFFFFFFFu;
         s_bits[i] = 0;
     }
     if (threadIdx.x == 0) s_bad = 0;
+    if constexpr (kLdsDesc) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
     __syncthreads();
-    const uint32_t x = blockIdx.x * kTileW + lane;
     bool invalid = false;
-    for (int row = (int)wv; row < kTileH; row += kMarkThreads / 64) {
-        const uint32_t y = blockIdx.y * kTileH + row;
-        if (y >= H) break;
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
         uint32_t ids[8];
 #pragma unroll
         for (int k = 0; k < 8; k++) ids[k] = 0xFFFFFFFFu;
-        if (x < W) {
-            const jpt_gpixel px = gbuf[(size_t)y * pitch + x];
-            LevelFoot foot[2];
-            int nf;
-            uint32_t tw;
-            const int st = pixel_footprint(levels, texs, n_tex, px, filter, foot, nf, tw);
-            if (st == PIX_INVALID) {
-                invalid = true;
-            } else if (st == PIX_VALID) {
+        LevelFoot foot[2];
+        int nf;
+        uint32_t tw;
+        int st;
+        if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px[r], filter, foot, nf, tw);
+        else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px[r], filter, foot, nf, tw);
+        if (st == PIX_INVALID) {
+            invalid = true;
+        } else if (st == PIX_VALID) {
 #pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    if (k >= nf || foot[k].lw == 0) continue;
-                    const LevelFoot &F = foot[k];
-                    if (filter == JPT_FILTER_NEAREST) {
-                        ids[4 * k] = block_of(F, F.x0, F.y0);
-                    } else {
-                        const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
-                        if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
-                        if (c1 && r0) ids[4 * k + 1] = block_of(F, F.x1, F.y0);
-                        if (c0 && r1) ids[4 * k + 2] = block_of(F, F.x0, F.y1);
-                        if (c1 && r1) ids[4 * k + 3] = block_of(F, F.x1, F.y1);
-                    }
+            for (int k = 0; k < 2; k++) {
+                if (k >= nf || foot[k].lw == 0) continue;
+                const LevelFoot &F = foot[k];
+                if (filter == JPT_FILTER_NEAREST) {
+                    ids[4 * k] = block_of(F, F.x0, F.y0);
+                } else {
+                    const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
+                    if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
+                    if (c1 && r0) ids[4 * k + 1] = block_of(F, F.x1, F.y0);
+                    if (c0 && r1) ids[4 * k + 2] = block_of(F, F.x0, F.y1);
+                    if (c1 && r1) ids[4 * k + 3] = block_of(F, F.x1, F.y1);
                 }
             }
         }
@@ -135,6 +145,48 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v, uint32_t lane) {
     return v;
 }
 
+// Exclusive prefix of this thread's packed sum within the whole scan: the
+// sums of earlier tiles plus the earlier threads of this tile.
+__device__ __forceinline__ uint64_t scan_base(const uint64_t *__restrict__ tile_sums, uint64_t mine) {
+    __shared__ uint64_t s_red[kScanThreads / 64];
+    __shared__ uint64_t s_wave[kScanThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t pre = 0;
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) pre += tile_sums[t];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pre += __shfl_xor(pre, d, 64);
+    if (lane == 0) s_red[wv] = pre;
+    const uint64_t incl = wave_incl_scan(mine, lane);
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    uint64_t base = 0;
+    for (int k = 0; k < kScanThreads / 64; k++) base += s_red[k];
+    for (uint32_t k = 0; k < wv; k++) base += s_wave[k];
+    return base + incl - mine;
+}
+
+// Sum of one value over the workgroup, written to tile_sums[blockIdx.x].
+__device__ __forceinline__ void tile_total(uint64_t s, uint64_t *__restrict__ tile_sums, uint32_t *vis_counter,
+                                           uint32_t nv) {
+    __shared__ uint64_t s_sum[kScanThreads / 64];
+    __shared__ uint32_t s_vis[kScanThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        s += __shfl_xor(s, d, 64);
+        nv += __shfl_xor(nv, d, 64);
+    }
+    if (lane == 0) { s_sum[wv] = s; s_vis[wv] = nv; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        uint32_t tv = 0;
+        for (int k = 0; k < kScanThreads / 64; k++) { t += s_sum[k]; tv += s_vis[k]; }
+        tile_sums[blockIdx.x] = t;
+        if (vis_counter && tv) atomicAdd(vis_counter, tv);
+    }
+}
+
 struct WordCounts {
     uint32_t newm[kWpt];
     uint32_t sub[kWpt];  // work items per block of that word's level
@@ -164,69 +216,63 @@ __device__ __forceinline__ uint64_t count_words(const uint32_t *__restrict__ vis
     return sum;
 }
 
+// Count the new blocks of each tile.  With a cache (LRU), visible resident
+// blocks are touched here: last_used of their slot = frame_no.
 __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restrict__ vis,
                                                         const uint32_t *__restrict__ resident,
                                                         const uint32_t *__restrict__ word_level,
                                                         const jpt_level_desc *__restrict__ levels, uint32_t n_words,
                                                         uint64_t *__restrict__ tile_sums,
-                                                        uint32_t *__restrict__ counters) {
-    __shared__ uint64_t s_sum[kScanThreads / 64];
-    __shared__ uint32_t s_vis[kScanThreads / 64];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                                                        uint32_t *__restrict__ counters,
+                                                        const uint32_t *__restrict__ slot_of,
+                                                        uint32_t *__restrict__ last_used, uint32_t frame_no) {
     WordCounts wc;
     uint32_t nv;
-    uint64_t s = count_words(vis, resident, word_level, levels, n_words,
-                             blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt, wc, nv);
+    const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
+    const uint64_t s = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
+    if (resident) {
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        s += __shfl_xor(s, d, 64);
-        nv += __shfl_xor(nv, d, 64);
+        for (int i = 0; i < kWpt; i++) {
+            if (w0 + i >= n_words) continue;
+            uint32_t m = vis[w0 + i] & resident[w0 + i];
+            while (m) {
+                const uint32_t b = (w0 + i) * 32 + __builtin_ctz(m);
+                m &= m - 1;
+                last_used[slot_of[b]] = frame_no;
+            }
+        }
     }
-    if (lane == 0) { s_sum[wv] = s; s_vis[wv] = nv; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        uint32_t tv = 0;
-        for (int k = 0; k < kScanThreads / 64; k++) { t += s_sum[k]; tv += s_vis[k]; }
-        tile_sums[blockIdx.x] = t;
-        if (tv) atomicAdd(counters + JPT_CTR_VISIBLE, tv);
-    }
+    tile_total(s, tile_sums, counters + JPT_CTR_VISIBLE, nv);
 }
 
+// List the new blocks: work items in ascending block id order and their
+// cache slots (no cache: the block's rank; LRU: popped off the free stack).
+template <bool kLru>
 __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restrict__ vis,
-                                                       const uint32_t *__restrict__ resident,
+                                                       uint32_t *__restrict__ resident,
                                                        const uint32_t *__restrict__ word_level,
                                                        const jpt_level_desc *__restrict__ levels, uint32_t n_words,
                                                        const uint64_t *__restrict__ tile_sums, uint32_t n_tiles,
                                                        uint32_t *__restrict__ work, uint32_t max_items,
                                                        uint32_t *__restrict__ slot_of, uint32_t n_slots,
-                                                       uint32_t *__restrict__ counters) {
-    __shared__ uint64_t s_red[kScanThreads / 64];
-    __shared__ uint64_t s_wave[kScanThreads / 64];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                                                       uint32_t *__restrict__ counters,
+                                                       const uint32_t *__restrict__ free_stack,
+                                                       const uint32_t *__restrict__ meta,
+                                                       uint32_t *__restrict__ owner,
+                                                       uint32_t *__restrict__ last_used, uint32_t frame_no) {
     const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
-    // this tile's words and the sums of all earlier tiles, loads in flight together
     WordCounts wc;
     uint32_t nv;
-    uint64_t mine = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
-    uint64_t pre = 0;
-    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kScanThreads) pre += tile_sums[t];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) pre += __shfl_xor(pre, d, 64);
-    if (lane == 0) s_red[wv] = pre;
-    const uint64_t incl = wave_incl_scan(mine, lane);
-    if (lane == 63) s_wave[wv] = incl;
-    __syncthreads();
-    uint64_t base = 0;
-    for (int k = 0; k < kScanThreads / 64; k++) base += s_red[k];
-    for (uint32_t k = 0; k < wv; k++) base += s_wave[k];
-    base += incl - mine;
+    const uint64_t mine = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
+    const uint64_t base = scan_base(tile_sums, mine);
+    const uint32_t top = kLru ? meta[JPT_META_TOP] : 0u;  // free slots after this frame's evictions
     uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
     bool overflow = false;
 #pragma unroll
     for (int i = 0; i < kWpt; i++) {
         uint32_t m = wc.newm[i];
         const uint32_t sub = wc.sub[i];
+        uint32_t placed = 0;
         while (m) {
             const uint32_t bit = __builtin_ctz(m);
             m &= m - 1;
@@ -234,11 +280,24 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
             const bool fits = item + sub <= max_items;
             for (uint32_t q = 0; q < sub; q++)
                 if (item + q < max_items) work[item + q] = (b << 2) | q;
-            if (slot_of) slot_of[b] = (blk < n_slots && fits) ? blk : JPT_SLOT_NONE;
-            overflow |= !fits || (slot_of && blk >= n_slots);
+            uint32_t slot = JPT_SLOT_NONE;
+            if (kLru) {
+                if (blk < top && fits) {
+                    slot = free_stack[top - 1 - blk];
+                    owner[slot] = b;
+                    last_used[slot] = frame_no;
+                    placed |= 1u << bit;
+                }
+                overflow |= !fits || blk >= top;
+            } else {
+                if (blk < n_slots && fits) slot = blk;
+                overflow |= !fits || (slot_of && blk >= n_slots);
+            }
+            if (slot_of) slot_of[b] = slot;
             item += sub;
             blk += 1;
         }
+        if (kLru && placed) resident[w0 + i] |= placed;  // this thread owns the word
     }
     if (overflow) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
     if (blockIdx.x == n_tiles - 1 && threadIdx.x == kScanThreads - 1) {
@@ -248,7 +307,223 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
     }
 }
 
+// ------------------------------------------------------------ LRU update
+// (paper: "Update Cache", with a slot capacity and oldest-first eviction in
+// place of evicting every block that was not visible.)
+constexpr int kAgeBins = JPT_LRU_MAX_AGE + 1;
+
+__device__ __forceinline__ bool bit_set(const uint32_t *__restrict__ mask, uint32_t b) {
+    return (mask[b >> 5] >> (b & 31)) & 1u;
+}
+
+__global__ __launch_bounds__(256) void k_lru_clear(uint32_t *__restrict__ tie_mask, uint32_t n_words,
+                                                   uint32_t *__restrict__ meta) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) tie_mask[w] = 0;
+    for (uint32_t k = i; k < (uint32_t)kAgeBins; k += gridDim.x * blockDim.x) meta[JPT_META_HIST + k] = 0;
+    if (i == 0) meta[JPT_META_EVICTED] = 0;
+}
+
+// Blocks to place and evictions needed.
+__global__ __launch_bounds__(256) void k_lru_plan(const uint64_t *__restrict__ tile_sums, uint32_t n_tiles,
+                                                  uint32_t *__restrict__ meta) {
+    __shared__ uint64_t s_part[4];
+    uint64_t s = 0;
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += 256) s += tile_sums[t];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t n_new = (uint32_t)((s_part[0] + s_part[1] + s_part[2] + s_part[3]) >> 32);
+        const uint32_t top = meta[JPT_META_TOP];
+        meta[JPT_META_NEW] = n_new;
+        meta[JPT_META_NEED] = n_new > top ? n_new - top : 0u;
+    }
+}
+
+__device__ __forceinline__ uint32_t age_bin(uint32_t frame_no, uint32_t last) {
+    const uint32_t a = frame_no - last;
+    return a < (uint32_t)JPT_LRU_MAX_AGE ? a : (uint32_t)JPT_LRU_MAX_AGE;
+}
+
+// Histogram of the ages of the eviction candidates (resident, not visible).
+__global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ owner,
+                                                  const uint32_t *__restrict__ last_used,
+                                                  const uint32_t *__restrict__ vis, uint32_t n_slots,
+                                                  uint32_t frame_no, uint32_t *__restrict__ meta) {
+    __shared__ uint32_t s_h[kAgeBins];
+    if (meta[JPT_META_NEED] == 0) return;
+    for (int k = threadIdx.x; k < kAgeBins; k += 256) s_h[k] = 0;
+    __syncthreads();
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
+        const uint32_t b = owner[s];
+        if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
+        atomicAdd(s_h + age_bin(frame_no, last_used[s]), 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kAgeBins; k += 256)
+        if (s_h[k]) atomicAdd(meta + JPT_META_HIST + k, s_h[k]);
+}
+
+// Oldest bins first: the bin where the evictions end and how many of its
+// blocks go (the smallest block ids).
+__global__ __launch_bounds__(256) void k_lru_threshold(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters) {
+    __shared__ uint32_t s_sum[256];
+    const uint32_t need = meta[JPT_META_NEED];
+    if (need == 0) return;
+    constexpr int kPer = kAgeBins / 256;
+    static_assert(kPer * 256 == kAgeBins, "age bins must split over 256 threads");
+    // thread t owns bins [kAgeBins - kPer (t+1), kAgeBins - kPer t): oldest first
+    const int hi = kAgeBins - kPer * (int)threadIdx.x;
+    uint32_t mine = 0;
+    for (int k = hi - kPer; k < hi; k++) mine += meta[JPT_META_HIST + k];
+    s_sum[threadIdx.x] = mine;
+    __syncthreads();
+    uint32_t before = 0;  // candidates in older bins
+    for (uint32_t t = 0; t < threadIdx.x; t++) before += s_sum[t];
+    if (before < need && before + mine >= need) {
+        uint32_t c = before;
+        for (int k = hi - 1; k >= hi - kPer; k--) {
+            const uint32_t h = meta[JPT_META_HIST + k];
+            if (c + h >= need) {
+                meta[JPT_META_ABIN] = (uint32_t)k;
+                meta[JPT_META_TIES] = need - c;
+                break;
+            }
+            c += h;
+        }
+    }
+    if (threadIdx.x == 255 && before + mine < need) {
+        // fewer candidates than new blocks: evict them all, the rest find no slot
+        meta[JPT_META_ABIN] = 0;
+        meta[JPT_META_TIES] = 0xFFFFFFFFu;
+        atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
+    }
+}
+
+__device__ __forceinline__ void evict(uint32_t s, uint32_t b, uint32_t *__restrict__ owner,
+                                      uint32_t *__restrict__ slot_of, uint32_t *__restrict__ resident,
+                                      uint32_t *__restrict__ free_stack, uint32_t *__restrict__ meta) {
+    owner[s] = JPT_SLOT_NONE;
+    slot_of[b] = JPT_SLOT_NONE;
+    atomicAnd(resident + (b >> 5), ~(1u << (b & 31)));
+    free_stack[atomicAdd(meta + JPT_META_TOP, 1u)] = s;
+    atomicAdd(meta + JPT_META_EVICTED, 1u);
+}
+
+// Evict every candidate older than the last bin; mark that bin's blocks.
+__global__ __launch_bounds__(256) void k_lru_evict(uint32_t *__restrict__ owner, const uint32_t *__restrict__ last_used,
+                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
+                                                   uint32_t frame_no, uint32_t *__restrict__ slot_of,
+                                                   uint32_t *__restrict__ resident, uint32_t *__restrict__ free_stack,
+                                                   uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta) {
+    if (meta[JPT_META_NEED] == 0) return;
+    const uint32_t abin = meta[JPT_META_ABIN], all = meta[JPT_META_TIES] == 0xFFFFFFFFu;
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
+        const uint32_t b = owner[s];
+        if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
+        const uint32_t bin = age_bin(frame_no, last_used[s]);
+        if (bin > abin || all) evict(s, b, owner, slot_of, resident, free_stack, meta);
+        else if (bin == abin) atomicOr(tie_mask + (b >> 5), 1u << (b & 31));
+    }
+}
+
+// Count the marked blocks of the last bin per scan tile.
+__global__ __launch_bounds__(kScanThreads) void k_tie_count(const uint32_t *__restrict__ tie_mask, uint32_t n_words,
+                                                            uint64_t *__restrict__ tile_sums,
+                                                            const uint32_t *__restrict__ meta) {
+    const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
+    uint64_t s = 0;
+    if (meta[JPT_META_NEED] != 0)
+#pragma unroll
+        for (int i = 0; i < kWpt; i++)
+            if (w0 + i < n_words) s += __popc(tie_mask[w0 + i]);
+    tile_total(s, tile_sums, nullptr, 0);
+}
+
+// Evict the marked blocks with the smallest ids, as many as the plan says.
+__global__ __launch_bounds__(kScanThreads) void k_tie_pick(const uint32_t *__restrict__ tie_mask, uint32_t n_words,
+                                                           const uint64_t *__restrict__ tile_sums,
+                                                           uint32_t *__restrict__ owner, uint32_t *__restrict__ slot_of,
+                                                           uint32_t *__restrict__ resident,
+                                                           uint32_t *__restrict__ free_stack,
+                                                           uint32_t *__restrict__ meta) {
+    const uint32_t need = meta[JPT_META_NEED];
+    const uint32_t ties = meta[JPT_META_TIES];
+    const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
+    uint32_t m[kWpt];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kWpt; i++) {
+        m[i] = (need != 0 && w0 + i < n_words) ? tie_mask[w0 + i] : 0u;
+        s += __popc(m[i]);
+    }
+    uint32_t rank = (uint32_t)scan_base(tile_sums, s);
+    if (need == 0 || ties == 0xFFFFFFFFu) return;
+#pragma unroll
+    for (int i = 0; i < kWpt; i++) {
+        while (m[i] && rank < ties) {
+            const uint32_t b = (w0 + i) * 32 + __builtin_ctz(m[i]);
+            m[i] &= m[i] - 1;
+            evict(slot_of[b], b, owner, slot_of, resident, free_stack, meta);
+            rank++;
+        }
+    }
+}
+
+// Pop the placed blocks off the free stack; report the update.
+__global__ void k_lru_finish(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters, uint32_t n_slots) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t top = meta[JPT_META_TOP], n_new = meta[JPT_META_NEW];
+    const uint32_t top2 = n_new < top ? top - n_new : 0u;
+    meta[JPT_META_TOP] = top2;
+    counters[JPT_CTR_EVICTED] = meta[JPT_META_EVICTED];
+    counters[JPT_CTR_RESIDENT] = n_slots - top2;
+}
+
+__global__ __launch_bounds__(256) void k_cache_reset(uint32_t *__restrict__ slot_of, uint32_t n_blocks,
+                                                     uint32_t *__restrict__ owner, uint32_t *__restrict__ last_used,
+                                                     uint32_t *__restrict__ free_stack, uint32_t n_slots,
+                                                     uint32_t *__restrict__ resident, uint32_t *__restrict__ tie_mask,
+                                                     uint32_t n_words, uint32_t *__restrict__ meta) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (uint32_t b = i; b < n_blocks; b += stride) slot_of[b] = JPT_SLOT_NONE;
+    for (uint32_t s = i; s < n_slots; s += stride) {
+        owner[s] = JPT_SLOT_NONE;
+        last_used[s] = 0;
+        free_stack[s] = n_slots - 1 - s;  // pops hand out slots 0, 1, 2, ...
+    }
+    for (uint32_t w = i; w < n_words; w += stride) { resident[w] = 0; tie_mask[w] = 0; }
+    for (uint32_t k = i; k < JPT_CACHE_META_WORDS; k += stride) meta[k] = k == JPT_META_TOP ? n_slots : 0u;
+}
+
+uint32_t grid_for(uint64_t n, uint32_t per_group, uint32_t cap) {
+    uint64_t g = (n + per_group - 1) / per_group;
+    if (g < 1) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+bool lru_ok(const jpt_cache *c) {
+    return c->texels && c->slot_of && c->owner && c->last_used && c->resident && c->free_stack && c->meta &&
+           c->tie_mask && c->n_slots > 0;
+}
+
 }  // namespace
+
+extern "C" jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, void *stream) {
+    if (!scene || !cache || cache->policy != JPT_CACHE_LRU || !lru_ok(cache) || scene->n_blocks == 0 ||
+        (scene->n_blocks & 31))
+        return JPT_E_ARG;
+    const uint32_t n_words = scene->n_blocks / 32;
+    hipLaunchKernelGGL(k_cache_reset, dim3(grid_for(scene->n_blocks > cache->n_slots ? scene->n_blocks : cache->n_slots,
+                                                    256, 4096)),
+                       dim3(256), 0, (hipStream_t)stream, cache->slot_of, scene->n_blocks, cache->owner,
+                       cache->last_used, cache->free_stack, cache->n_slots, cache->resident, cache->tie_mask, n_words,
+                       cache->meta);
+    HIP_CHECK_LAUNCH();
+    return JPT_OK;
+}
 
 extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                                       jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
@@ -259,33 +534,69 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         (scene->n_blocks & 31) || scene->n_blocks > (1u << 29))
         return JPT_E_ARG;
     if (!frame->vis || !frame->work || !frame->counters || !frame->scan) return JPT_E_ARG;
-    if (cache && cache->policy != JPT_CACHE_NONE) return JPT_E_ARG;  // LRU: not available in this build
+    const bool lru = cache && cache->policy == JPT_CACHE_LRU;
+    if (cache && cache->policy > JPT_CACHE_LRU) return JPT_E_ARG;
+    if (lru && !lru_ok(cache)) return JPT_E_ARG;
     for (uint32_t v = 0; v < n_views; v++)
         if (!views[v].gbuf || views[v].pitch < views[v].width) return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n_words = scene->n_blocks / 32;
     const uint32_t n_tiles = (n_words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
-    uint32_t clear_groups = (n_words + 255) / 256;
-    if (clear_groups > 1024) clear_groups = 1024;
-    if (clear_groups == 0) clear_groups = 1;
-    hipLaunchKernelGGL(k_clear, dim3(clear_groups), dim3(256), 0, st, frame->vis, n_words, frame->counters);
+    uint64_t *scan2 = frame->scan + n_tiles;  // second scan of the frame (LRU ties)
+    const uint32_t f = frame->frame_no;
+    hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis, n_words,
+                       frame->counters);
     HIP_CHECK_LAUNCH();
+    if (lru) {
+        hipLaunchKernelGGL(k_lru_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, cache->tie_mask,
+                           n_words, cache->meta);
+        HIP_CHECK_LAUNCH();
+    }
     for (uint32_t v = 0; v < n_views; v++) {
         const jpt_view &V = views[v];
         if (V.width == 0 || V.height == 0) continue;
         dim3 grid((V.width + kTileW - 1) / kTileW, (V.height + kTileH - 1) / kTileH);
-        hipLaunchKernelGGL(k_mark, grid, dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
-                           scene->n_textures, V.gbuf, V.width, V.height, V.pitch, filter, frame->vis,
-                           frame->counters);
+        if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
+            hipLaunchKernelGGL(k_mark<true>, grid, dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
+                               scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
+                               frame->vis, frame->counters);
+        else
+            hipLaunchKernelGGL(k_mark<false>, grid, dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
+                               scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
+                               frame->vis, frame->counters);
         HIP_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, (const uint32_t *)nullptr,
-                       scene->word_level, scene->levels, n_words, frame->scan, frame->counters);
+    hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis,
+                       lru ? cache->resident : (const uint32_t *)nullptr, scene->word_level, scene->levels, n_words,
+                       frame->scan, frame->counters, lru ? cache->slot_of : (const uint32_t *)nullptr,
+                       lru ? cache->last_used : (uint32_t *)nullptr, f);
     HIP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_emit, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, (const uint32_t *)nullptr,
-                       scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
-                       frame->max_items, cache ? cache->slot_of : nullptr, cache ? cache->n_slots : 0u,
-                       frame->counters);
+    if (lru) {
+        const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
+        hipLaunchKernelGGL(k_lru_plan, dim3(1), dim3(256), 0, st, frame->scan, n_tiles, cache->meta);
+        hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                           cache->n_slots, f, cache->meta);
+        hipLaunchKernelGGL(k_lru_threshold, dim3(1), dim3(256), 0, st, cache->meta, frame->counters);
+        hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                           cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
+                           cache->meta);
+        hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                           cache->meta);
+        hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                           cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
+        HIP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_emit<true>, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
+                           scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
+                           frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
+                           cache->meta, cache->owner, cache->last_used, f);
+        hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots);
+    } else {
+        hipLaunchKernelGGL(k_emit<false>, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, (uint32_t *)nullptr,
+                           scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
+                           frame->max_items, cache ? cache->slot_of : nullptr, cache ? cache->n_slots : 0u,
+                           frame->counters, (const uint32_t *)nullptr, (const uint32_t *)nullptr,
+                           (uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    }
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }

@@ -2,85 +2,157 @@
 // the cache slots of their blocks and blends them with integer weights.
 // Every tap a pixel reads was marked, so no clamping at undecoded MCU borders
 // is needed (the footprint marking makes the result exact).
+//
+// A workgroup shades a 64 x 16 pixel tile, 4 rows per lane.  The scene's
+// sampling descriptors are cached in LDS, and for each lane all tap slot
+// lookups are issued before any texel load, and all texel loads before any
+// blend, so that a lane keeps up to 32 independent loads in flight.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
 
 namespace {
 
-__device__ __forceinline__ bool fetch(const uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ texels,
-                                      const LevelFoot &F, uint32_t x, uint32_t y, uint32_t &t) {
-    const uint32_t slot = slot_of[block_of(F, x, y)];
-    if (slot == JPT_SLOT_NONE) return false;
-    t = texels[(size_t)slot * 256 + (y & 15) * 16 + (x & 15)];
-    return true;
-}
+constexpr int kThreads = 256;
+constexpr int kTileW = 64, kTileH = 16;
+constexpr int kRows = kTileH / (kThreads / 64);
 
-// Weighted sum of one level's taps, rounded: (sum texel * w + 32768) >> 16.
-__device__ __forceinline__ bool level_sample(const uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ texels,
-                                             const LevelFoot &F, uint32_t filter, uint32_t rgb[3]) {
-    if (filter == JPT_FILTER_NEAREST) {
-        uint32_t t;
-        if (!fetch(slot_of, texels, F, F.x0, F.y0, t)) return false;
-        rgb[0] = t & 255; rgb[1] = (t >> 8) & 255; rgb[2] = (t >> 16) & 255;
-        return true;
-    }
-    const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
-    const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
-    uint32_t acc[3] = {0, 0, 0};
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-#pragma unroll
-        for (int a = 0; a < 2; a++) {
-            const uint32_t w = wx[a] * wy[b];
-            if (w == 0) continue;
-            uint32_t t;
-            if (!fetch(slot_of, texels, F, xs[a], ys[b], t)) return false;
-            acc[0] += (t & 255) * w;
-            acc[1] += ((t >> 8) & 255) * w;
-            acc[2] += ((t >> 16) & 255) * w;
-        }
-#pragma unroll
-    for (int c = 0; c < 3; c++) rgb[c] = (acc[c] + 32768u) >> 16;
-    return true;
-}
+template <uint32_t kFilter>
+struct FilterTraits {
+    static constexpr int kTaps = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
+};
 
-__global__ __launch_bounds__(256) void k_resolve(const jpt_level_desc *__restrict__ levels,
-                                                 const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
-                                                 const jpt_gpixel *__restrict__ gbuf, uint32_t W, uint32_t H,
-                                                 uint32_t pitch, uint32_t filter, const uint32_t *__restrict__ slot_of,
-                                                 const uint32_t *__restrict__ texels, uint32_t *__restrict__ frame,
-                                                 uint32_t frame_pitch) {
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t x = blockIdx.x * 16 + (wv & 1) * 8 + (lane & 7);
-    const uint32_t y = blockIdx.y * 16 + (wv >> 1) * 8 + (lane >> 3);
-    if (x >= W || y >= H) return;
-    const jpt_gpixel px = gbuf[(size_t)y * pitch + x];
+// Taps of one pixel: block id, texel offset inside the block's slot and
+// weight (0 = unused tap).  Weights of one level sum to 65536.
+template <int kTaps>
+struct Taps {
+    uint32_t blk[kTaps], off[kTaps], w[kTaps];
+};
+
+template <uint32_t kFilter, class Desc>
+__device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const jpt_gpixel &px,
+                                          Taps<FilterTraits<kFilter>::kTaps> &T, uint32_t &tw, int &nf) {
+    constexpr int kTaps = FilterTraits<kFilter>::kTaps;
+#pragma unroll
+    for (int t = 0; t < kTaps; t++) { T.blk[t] = 0; T.off[t] = 0; T.w[t] = 0; }
     LevelFoot foot[2];
-    int nf;
-    uint32_t tw;
-    const int st = pixel_footprint(levels, texs, n_tex, px, filter, foot, nf, tw);
-    uint32_t out;
-    if (st == PIX_BACKGROUND) {
-        out = 0;
-    } else if (st == PIX_INVALID) {
-        out = JPT_TEXEL_INVALID;
-    } else {
-        uint32_t a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-        bool ok = true;
-        if (foot[0].lw) ok = level_sample(slot_of, texels, foot[0], filter, a);
-        if (ok && nf == 2 && foot[1].lw) ok = level_sample(slot_of, texels, foot[1], filter, b);
-        if (!ok) {
+    const int st = pixel_footprint(D, n_tex, px, kFilter, foot, nf, tw);
+    if (st != PIX_VALID) return st;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (kFilter != JPT_FILTER_TRILINEAR && k > 0) break;
+        if (k >= nf || foot[k].lw == 0) continue;
+        const LevelFoot &F = foot[k];
+        if (kFilter == JPT_FILTER_NEAREST) {
+            T.blk[0] = block_of(F, F.x0, F.y0);
+            T.off[0] = (F.y0 & 15) * 16 + (F.x0 & 15);
+            T.w[0] = 65536;
+        } else {
+            const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
+            const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++) {
+                    const int t = 4 * k + 2 * b + a;
+                    T.blk[t] = block_of(F, xs[a], ys[b]);
+                    T.off[t] = (ys[b] & 15) * 16 + (xs[a] & 15);
+                    T.w[t] = wx[a] * wy[b];
+                }
+        }
+    }
+    return PIX_VALID;
+}
+
+template <uint32_t kFilter, bool kLdsDesc>
+__global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__restrict__ levels,
+                                                      const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
+                                                      uint32_t n_lev, const jpt_gpixel *__restrict__ gbuf,
+                                                      uint32_t W, uint32_t H, uint32_t pitch,
+                                                      const uint32_t *__restrict__ slot_of,
+                                                      const uint32_t *__restrict__ texels,
+                                                      uint32_t *__restrict__ frame, uint32_t frame_pitch) {
+    constexpr int kTaps = FilterTraits<kFilter>::kTaps;
+    __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
+    __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t x = blockIdx.x * kTileW + lane;
+    jpt_gpixel px[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+        const uint32_t y = blockIdx.y * kTileH + wv + r * (kThreads / 64);
+        px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+    }
+    if constexpr (kLdsDesc) {
+        load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
+        __syncthreads();
+    }
+    for (int r = 0; r < kRows; r++) {
+        const uint32_t y = blockIdx.y * kTileH + wv + r * (kThreads / 64);
+        Taps<kTaps> T;
+        uint32_t tw;
+        int nf, st;
+        if constexpr (kLdsDesc) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
+        else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
+        // all slot lookups of the pixel, then all texel loads
+        uint32_t slot[kTaps], tex[kTaps];
+#pragma unroll
+        for (int t = 0; t < kTaps; t++) slot[t] = T.w[t] ? slot_of[T.blk[t]] : 0u;
+#pragma unroll
+        for (int t = 0; t < kTaps; t++)
+            tex[t] = (T.w[t] && slot[t] != JPT_SLOT_NONE) ? texels[(size_t)slot[t] * 256 + T.off[t]] : 0u;
+        if (x >= W || y >= H) continue;
+        uint32_t out;
+        if (st == PIX_BACKGROUND) {
+            out = 0;
+        } else if (st == PIX_INVALID) {
             out = JPT_TEXEL_INVALID;
         } else {
-            if (nf == 2) {
+            bool missing = false;
+            uint32_t lvl[2][3] = {{0, 0, 0}, {0, 0, 0}};
+            constexpr int kLevels = kTaps == 8 ? 2 : 1, kPer = kTaps == 1 ? 1 : 4;
 #pragma unroll
-                for (int c = 0; c < 3; c++) a[c] = (a[c] * (256 - tw) + b[c] * tw + 128) >> 8;
+            for (int k = 0; k < kLevels; k++) {
+                uint32_t acc[3] = {0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < kPer; j++) {
+                    const int t = k * kPer + j;
+                    const uint32_t w = T.w[t];
+                    missing |= (w != 0) && slot[t] == JPT_SLOT_NONE;
+                    const uint32_t v = tex[t];
+                    acc[0] += (v & 255) * w;
+                    acc[1] += ((v >> 8) & 255) * w;
+                    acc[2] += ((v >> 16) & 255) * w;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; c++) lvl[k][c] = (acc[c] + 32768u) >> 16;
             }
-            out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
+            if (missing) {
+                out = JPT_TEXEL_INVALID;
+            } else {
+                uint32_t a[3] = {lvl[0][0], lvl[0][1], lvl[0][2]};
+                if (kFilter == JPT_FILTER_TRILINEAR && nf == 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) a[c] = (lvl[0][c] * (256 - tw) + lvl[1][c] * tw + 128) >> 8;
+                }
+                out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
+            }
         }
+        frame[(size_t)y * frame_pitch + x] = out;
     }
-    frame[(size_t)y * frame_pitch + x] = out;
+}
+
+template <uint32_t kFilter>
+void launch(const jpt_scene *scene, const jpt_view &V, const jpt_cache *cache, hipStream_t st) {
+    dim3 grid((V.width + kTileW - 1) / kTileW, (V.height + kTileH - 1) / kTileH);
+    if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
+        hipLaunchKernelGGL((k_resolve<kFilter, true>), grid, dim3(kThreads), 0, st, scene->levels, scene->textures,
+                           scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, cache->slot_of,
+                           cache->texels, V.frame, V.frame_pitch);
+    else
+        hipLaunchKernelGGL((k_resolve<kFilter, false>), grid, dim3(kThreads), 0, st, scene->levels, scene->textures,
+                           scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, cache->slot_of,
+                           cache->texels, V.frame, V.frame_pitch);
 }
 
 }  // namespace
@@ -100,10 +172,9 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
     for (uint32_t v = 0; v < n_views; v++) {
         const jpt_view &V = views[v];
         if (V.width == 0 || V.height == 0) continue;
-        dim3 grid((V.width + 15) / 16, (V.height + 15) / 16);
-        hipLaunchKernelGGL(k_resolve, grid, dim3(256), 0, st, scene->levels, scene->textures, scene->n_textures,
-                           V.gbuf, V.width, V.height, V.pitch, filter, cache->slot_of, cache->texels, V.frame,
-                           V.frame_pitch);
+        if (filter == JPT_FILTER_NEAREST) launch<JPT_FILTER_NEAREST>(scene, V, cache, st);
+        else if (filter == JPT_FILTER_BILINEAR) launch<JPT_FILTER_BILINEAR>(scene, V, cache, st);
+        else launch<JPT_FILTER_TRILINEAR>(scene, V, cache, st);
         HIP_CHECK_LAUNCH();
     }
     return JPT_OK;

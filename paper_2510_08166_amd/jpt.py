@@ -30,7 +30,8 @@ N_COUNTERS = 16
 ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL = 1, 2, 4
 SLOT_NONE = 0xFFFFFFFF
 TEXEL_INVALID = 0xFFFF00FF
-ITEM_COEFS = 6 * 64
+ITEMS_DU = 6
+ITEM_COEFS = ITEMS_DU * 64
 RECORD_BYTES = 64
 TABLESET_WORDS = 6656
 
@@ -73,7 +74,11 @@ class FrameC(ctypes.Structure):
 
 class CacheC(ctypes.Structure):
     _fields_ = [("texels", vp), ("slot_of", vp), ("owner", vp), ("last_used", vp), ("resident", vp),
-                ("n_slots", u32), ("policy", u32)]
+                ("free_stack", vp), ("meta", vp), ("tie_mask", vp), ("n_slots", u32), ("policy", u32)]
+
+
+LRU_MAX_AGE = 1023
+CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1
 
 
 class TuningC(ctypes.Structure):
@@ -95,6 +100,10 @@ SIGNATURES = {
     "jpt_entropy_decode": (ctypes.c_int32, [vp, vp, vp, vp]),
     "jpt_idct_color": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_resolve": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
+    "jpt_cache_reset": (ctypes.c_int32, [vp, vp, vp]),
+    "jpt_dequantize": (ctypes.c_int32, [vp, vp, vp, vp]),
+    "jpt_fwd_float": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp]),
+    "jpt_backward": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp]),
     "jpt_version": (u32, []),
     "jpt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
 }
@@ -315,13 +324,36 @@ class Frame:
 class Cache:
     """Decoded-block cache: slots of 16x16 RGBA8 texels and the block -> slot table."""
 
-    def __init__(self, scene: DeviceScene, n_slots: int, policy: int = CACHE_NONE):
+    def __init__(self, scene: DeviceScene, n_slots: int, policy: int = CACHE_NONE, stream=None):
         torch = _torch()
         d = scene.device
         self.texels = torch.zeros(max(1, n_slots) * 256, dtype=torch.int32, device=d)
         self.slot_of = torch.full((scene.n_blocks,), -1, dtype=torch.int32, device=d)
-        self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), None, None, None, n_slots, policy)
         self.n_slots = n_slots
+        self.policy = policy
+        if policy == CACHE_LRU:
+            n_words = scene.n_blocks // 32
+            self.owner = torch.empty(n_slots, dtype=torch.int32, device=d)
+            self.last_used = torch.empty(n_slots, dtype=torch.int32, device=d)
+            self.free_stack = torch.empty(n_slots, dtype=torch.int32, device=d)
+            self.resident = torch.empty(n_words, dtype=torch.int32, device=d)
+            self.tie_mask = torch.empty(n_words, dtype=torch.int32, device=d)
+            self.meta = torch.empty(CACHE_META_WORDS, dtype=torch.int32, device=d)
+            self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), self.owner.data_ptr(),
+                            self.last_used.data_ptr(), self.resident.data_ptr(), self.free_stack.data_ptr(),
+                            self.meta.data_ptr(), self.tie_mask.data_ptr(), n_slots, policy)
+            self.reset(scene, stream)
+        else:
+            self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), None, None, None, None, None, None,
+                            n_slots, policy)
+
+    def reset(self, scene: DeviceScene, stream=None):
+        _check("jpt_cache_reset", lib().jpt_cache_reset(ctypes.byref(scene.c), ctypes.byref(self.c),
+                                                        stream if stream is not None else current_stream()))
+
+    def resident_blocks(self) -> np.ndarray:
+        m = self.resident.cpu().numpy().view(np.uint32)
+        return np.nonzero(np.unpackbits(m.view(np.uint8), bitorder="little"))[0].astype(np.uint32)
 
 
 class Views:
@@ -386,7 +418,8 @@ def resolve(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Ca
 class Renderer:
     """One frame of the plain form: mark -> decode -> resolve on the current stream."""
 
-    def __init__(self, textures, gbufs, filt, device="cuda", max_items=None, n_slots=None, host=None):
+    def __init__(self, textures, gbufs, filt, device="cuda", max_items=None, n_slots=None, host=None,
+                 policy=CACHE_NONE):
         self.host = host or HostScene(textures)
         self.scene = DeviceScene(self.host, device)
         self.views = Views(gbufs, device)
@@ -395,10 +428,20 @@ class Renderer:
         cap = self.host.n_items_total
         self.max_items = int(max_items or min(cap, taps * 4 * self.views.n_pixels + 64))
         self.frame = Frame(self.scene, self.max_items)
-        self.cache = Cache(self.scene, int(n_slots or min(self.host.n_blocks, self.max_items)), CACHE_NONE)
+        self.cache = Cache(self.scene, int(n_slots or min(self.host.n_blocks, self.max_items)), policy)
+        self.frame_no = 0
+
+    def set_views(self, gbufs):
+        """Load new G-buffers (same sizes) into the existing view buffers."""
+        torch = _torch()
+        for gt, g in zip(self.views.gbufs, gbufs):
+            H, W = g.shape
+            gt.copy_(torch.from_numpy(np.ascontiguousarray(g).view(np.int32).reshape(H, W, 4).copy()))
 
     def mark(self, stream=None):
+        self.frame.c.frame_no = self.frame_no
         mark_blocks(self.scene, self.views, self.filter, self.frame, self.cache, stream=stream)
+        self.frame_no += 1
 
     def decode(self, stream=None, idct_mode=IDCT_MFMA_F16):
         decode_blocks(self.scene, self.frame, self.cache, idct_mode, stream=stream)
@@ -410,3 +453,94 @@ class Renderer:
         self.mark(stream)
         self.decode(stream)
         self.resolve(stream)
+
+
+class DiffFrame:
+    """Differentiable form over a Renderer's current frame.
+
+    After mark + decode, the leaf is F = the dequantised coefficients of this
+    frame's work items ([n_items, 6, 64] float32, natural order); forward()
+    maps F to the float frame ([n_pixels of all views, 3]) with the rounding
+    and clamping of the 8-bit path removed, backward() applies the
+    hand-written adjoint.  Needs JPT_CACHE_NONE, so that every block the
+    views read is a work item of the frame."""
+
+    def __init__(self, r: "Renderer"):
+        if r.cache.policy != CACHE_NONE:
+            raise ValueError("the differentiable form needs a frame-local cache (JPT_CACHE_NONE)")
+        torch = _torch()
+        self.r = r
+        d = r.scene.device
+        n = max(1, r.cache.n_slots)
+        self.texel_f = torch.empty(n * 768, dtype=torch.float32, device=d)
+        self.dtexel = torch.empty(n * 768, dtype=torch.int64, device=d)
+        self.n_pixels = r.views.n_pixels
+
+    def n_items(self) -> int:
+        return int(self.r.frame.counters_host()[CTR_ITEMS])
+
+    def dequantize(self, stream=None):
+        torch = _torch()
+        F = torch.empty((self.n_items(), ITEMS_DU, 64), dtype=torch.float32, device=self.r.scene.device)
+        if F.numel():
+            _check("jpt_dequantize", lib().jpt_dequantize(ctypes.byref(self.r.scene.c), ctypes.byref(self.r.frame.c),
+                                                          vp(F.data_ptr()), stream or current_stream()))
+        return F
+
+    def forward(self, F, stream=None):
+        torch = _torch()
+        F = F.contiguous()
+        self._check_F(F)
+        frame_f = torch.empty((self.n_pixels, 3), dtype=torch.float32, device=F.device)
+        r = self.r
+        _check("jpt_fwd_float", lib().jpt_fwd_float(
+            ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
+            vp(F.data_ptr()), vp(self.texel_f.data_ptr()), vp(frame_f.data_ptr()), stream or current_stream()))
+        return frame_f
+
+    def backward(self, dframe, F_shape, stream=None):
+        torch = _torch()
+        dframe = dframe.contiguous().float()
+        if tuple(dframe.shape) != (self.n_pixels, 3):
+            raise ValueError("dframe shape %s" % (tuple(dframe.shape),))
+        dF = torch.empty(F_shape, dtype=torch.float32, device=dframe.device)
+        r = self.r
+        _check("jpt_backward", lib().jpt_backward(
+            ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
+            vp(dframe.data_ptr()), vp(self.dtexel.data_ptr()), vp(dF.data_ptr()), stream or current_stream()))
+        return dF
+
+    def _check_F(self, F):
+        torch = _torch()
+        if F.dtype != torch.float32 or F.dim() != 3 or F.shape[1:] != (ITEMS_DU, 64):
+            raise ValueError("F must be float32 [n_items, 6, 64]")
+        if F.shape[0] > self.r.max_items:
+            raise ValueError("more items than the frame holds")
+
+    def __call__(self, F):
+        return _diff_fn().apply(F, self)
+
+
+_DIFF_FN = None
+
+
+def _diff_fn():
+    """torch.autograd.Function whose forward and backward are jpt_fwd_float
+    and jpt_backward."""
+    global _DIFF_FN
+    if _DIFF_FN is None:
+        torch = _torch()
+
+        class DiffResolve(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, F, diff):
+                ctx.diff = diff
+                ctx.F_shape = tuple(F.shape)
+                return diff.forward(F.detach())
+
+            @staticmethod
+            def backward(ctx, dframe):
+                return ctx.diff.backward(dframe, ctx.F_shape), None
+
+        _DIFF_FN = DiffResolve
+    return _DIFF_FN

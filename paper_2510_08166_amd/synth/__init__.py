@@ -235,3 +235,8 @@ def make_textures(specs, keep_rgb=False, threads: int | None = None):
 
 def seed_ints(seed: int, n: int) -> list[int]:
     return [int(s.generate_state(1, np.uint64)[0]) for s in np.random.SeedSequence(seed).spawn(n)]
+
+
+def target_frame(seed: int, H: int, W: int) -> np.ndarray:
+    """Seeded target image for an L2 loss: [H, W, 3] float32, uniform in [0, 255]."""
+    return np.random.default_rng(seed).uniform(0.0, 255.0, (H, W, 3)).astype(np.float32)

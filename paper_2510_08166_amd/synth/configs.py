@@ -7,6 +7,7 @@ and repeated as well as non-repeating uv mappings.
             that maps pixel centres 1:1 onto texel centres, nearest filter.
   1080p     32 textures of 2048x2048, q ~ U{50..90}, 4:2:0, 8 levels each
             (2048 .. 16); 1920x1080 frame from 200 random quads, bilinear.
+  diff1080  the differentiable-form scene: as 1080p with every texture at q75.
   reduced   the 1080p recipe at a size the CPU checker finishes quickly
             (used by tests only).
 """
@@ -64,7 +65,54 @@ def frame1080(keep_rgb=False) -> Workload:
                       name="1080p: 32 x 2048^2 q50-90 4:2:0 8 levels, 200 quads, bilinear")
 
 
+def diff1080(keep_rgb=False) -> Workload:
+    """Differentiable-form scene: 32 textures of 2048x2048 at q75, 4:2:0,
+    8 levels; 1920x1080 frame from 200 quads, bilinear."""
+    return quad_scene(5, 32, 2048, 75, 75, 8, 1920, 1080, 200, keep_rgb=keep_rgb,
+                      name="diff 1080p: 32 x 2048^2 q75 4:2:0 8 levels, 200 quads, bilinear")
+
+
 def reduced(seed=7, n_tex=4, side=256, W=320, H=200, n_quads=24, n_levels=5, filt=FILTER_BILINEAR,
             keep_rgb=False) -> Workload:
     return quad_scene(seed, n_tex, side, 50, 90, n_levels, W, H, n_quads, filt=filt, keep_rgb=keep_rgb,
                       name="reduced %dx%d^2, %dx%d" % (n_tex, side, W, H))
+
+
+def drift_transforms(rng: np.random.Generator, W: int, H: int, n_frames: int):
+    """Seeded camera drift: per frame a random-walk step of translation
+    ~ N(0, 1% of W), rotation ~ N(0, 0.5 deg), zoom ~ exp N(0, 0.02)."""
+    from . import similarity
+    tx = ty = rot = 0.0
+    zoom = 1.0
+    out = []
+    for f in range(n_frames):
+        if f:
+            tx += rng.normal(0, 0.01 * W); ty += rng.normal(0, 0.01 * W)
+            rot += rng.normal(0, 0.5); zoom *= float(np.exp(rng.normal(0, 0.02)))
+        out.append(similarity(tx, ty, rot, zoom, W, H))
+    return out
+
+
+def heavy(seed=3, n_tex=256, sides=(512, 1024, 2048, 4096, 8192), q_lo=40, q_hi=95, W=3840, H=2160, n_quads=2000,
+          n_frames=8, keep_rgb=False, name=None) -> Workload:
+    """Heavy recipe: textures of random power-of-two sides, q ~ U{q_lo..q_hi},
+    4:2:0 / 4:4:4 half and half, full mip chains; a quad scene seen over
+    n_frames frames of seeded camera drift; trilinear.  Views = frames."""
+    from . import make_textures, random_quads, rasterise
+    ss = np.random.SeedSequence(seed)
+    tex_seq, prm_seq, scene_seq, cam_seq = ss.spawn(4)
+    tex_seeds = [int(s.generate_state(1, np.uint64)[0]) for s in tex_seq.spawn(n_tex)]
+    prm = np.random.default_rng(prm_seq)
+    side = prm.choice(np.array(sides), n_tex)
+    qs = prm.integers(q_lo, q_hi + 1, n_tex)
+    smp = np.where(prm.random(n_tex) < 0.5, 420, 444)
+    specs = [(tex_seeds[i], int(side[i]), int(side[i]), int(qs[i]), int(smp[i]), None) for i in range(n_tex)]
+    textures = make_textures(specs, keep_rgb=keep_rgb)
+    rng = np.random.default_rng(scene_seq)
+    sizes = {i: (float(side[i]), float(side[i])) for i in range(n_tex)}
+    quads = random_quads(rng, W, H, n_quads, list(range(n_tex)), sizes)
+    xf = drift_transforms(np.random.default_rng(cam_seq), W, H, n_frames)
+    frames = [rasterise(W, H, quads, x) for x in xf]
+    return Workload(name or "heavy %d tex, %dx%d, %d frames" % (n_tex, W, H, n_frames), textures, frames,
+                    FILTER_TRILINEAR, dict(quads=quads, qualities=qs.tolist(), sides=side.tolist(),
+                                           sampling=smp.tolist()))

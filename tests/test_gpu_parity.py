@@ -164,3 +164,46 @@ def test_pil_files_with_optimised_tables(gpu):
     from paper_2510_08166_amd import jpt
     assert len(jpt.HostScene(texs).tablesets) > 1
     full_parity(wl)
+
+
+def test_lru_cache_over_drifting_frames(gpu):
+    """LRU cache under camera drift (mixed 4:2:0 / 4:4:4, full mip chains,
+    trilinear): per frame, the decoded set, the number of evictions and the
+    resident set equal the oracle's simulator; frames match the oracle."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    wl = configs.heavy(seed=31, n_tex=12, sides=(64, 128, 256), W=320, H=200, n_quads=40, n_frames=6)
+    osc = oracle.Scene(wl.textures)
+    vis_sets = [parity.visible_blocks(osc, [g], wl.filter) for g in wl.views]
+    cap = max(len(v) for v in vis_sets) + 24          # small: forces evictions every frame
+    r = jpt.Renderer(wl.textures, [wl.views[0]], wl.filter, n_slots=cap, policy=jpt.CACHE_LRU)
+    sim = oracle.LruSim(cap)
+    lc = parity.LevelCache(osc)
+    evictions = 0
+    for f, g in enumerate(wl.views):
+        r.set_views([g])
+        r.render()
+        torch.cuda.synchronize()
+        ctr = r.frame.counters_host()
+        new, ev = sim.step(f, vis_sets[f])
+        evictions += len(ev)
+        items = r.frame.work_items()
+        print("frame %d: visible %d new %d evicted %d err %x" % (f, ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_NEW],
+                                                                ctr[jpt.CTR_EVICTED], ctr[jpt.CTR_ERROR]), flush=True)
+        assert ctr[jpt.CTR_ERROR] == 0
+        assert ctr[jpt.CTR_VISIBLE] == len(vis_sets[f])
+        assert np.array_equal(items, parity.expected_items(osc, np.array(new, np.uint32)))
+        assert ctr[jpt.CTR_EVICTED] == len(ev)
+        assert np.array_equal(r.cache.resident_blocks(), np.array(sorted(sim.last_used), np.uint32))
+        assert ctr[jpt.CTR_RESIDENT] == len(sim.last_used)
+        # texels of every visible block, fetched through slot_of
+        slot_of = r.cache.slot_of.cpu().numpy().view(np.uint32)
+        tex = r.cache.texels.cpu().numpy().view(np.uint32).reshape(-1, 256)
+        blocks = vis_sets[f]
+        assert (slot_of[blocks] != jpt.SLOT_NONE).all()
+        tiles = tex[slot_of[blocks]]
+        maxd, nmis, tie, n = parity.check_texels(lc, blocks, tiles)
+        assert maxd <= 1 and tie < 0.01
+        ref, bad = osc.resolve(g, wl.filter, parity.levels_from_tiles(osc, blocks, tiles))
+        assert np.array_equal(r.views.frame_host(), ref)
+    assert evictions > 0
