@@ -111,124 +111,207 @@ def cpu_baseline(wl, budget_s=20.0):
     return {"value": round(ms, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle", "sample": sample}
 
 
+def time_graph(r, steps, warmup):
+    """Capture one frame of every view (jpt_graph_capture) on a side stream and
+    time `steps` replays.  Returns (wall ms per frame, per-frame GPU ms)."""
+    import numpy as np
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = r.capture(side)
+    for _ in range(warmup):
+        g.launch()
+    side.synchronize()
+    with torch.cuda.stream(side):
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gev[0].record(side)
+        for s_ in range(steps):
+            g.launch()
+            gev[s_ + 1].record(side)
+        side.synchronize()
+        wall = time.perf_counter() - t0
+    g.close()
+    gpu = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(steps)])
+    return 1000.0 * wall / steps, gpu
+
+
+def time_phases(r, steps):
+    """Eager frames with HIP events between the four C-ABI calls, all on the
+    current stream: per-phase GPU milliseconds, median over steps."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in evs:
+        e[0].record()
+        r.mark()
+        e[1].record()
+        jpt.entropy_decode(r.scene, r.frame, r.tuning)
+        e[2].record()
+        jpt.idct_color(r.scene, r.frame, r.cache, r.idct_mode, r.tuning)
+        e[3].record()
+        r.resolve()
+        e[4].record()
+    torch.cuda.synchronize()
+    eager_ms = 1000.0 * (time.perf_counter() - t0) / steps
+    ph = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e in evs])
+    return eager_ms, np.median(ph, axis=0)
+
+
+PHASES = ["mark+compact", "entropy", "idct", "resolve"]
+
+
+def plain_form(args, wl, label, policy=0, n_slots=None):
+    """The plain form on one workload: one step = one frame of all its views."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    t0 = time.perf_counter()
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, device="cuda:0", policy=policy, n_slots=n_slots)
+    torch.cuda.synchronize()
+    log("index built and uploaded in %.1f s" % (time.perf_counter() - t0))
+    if policy == jpt.CACHE_LRU:
+        raise SystemExit("use the heavy leg for LRU")
+    for _ in range(args.warmup):
+        r.render()
+    torch.cuda.synchronize()
+    ctr = r.frame.counters_host().copy()
+    if ctr[jpt.CTR_ERROR]:
+        raise SystemExit("device error flags %x" % ctr[jpt.CTR_ERROR])
+    ms_per_step, gpu_frame = time_graph(r, args.steps, args.warmup)
+    ctr2 = r.frame.counters_host()
+    if ctr2[jpt.CTR_ERROR] or ctr2[jpt.CTR_NEW] != ctr[jpt.CTR_NEW]:
+        raise SystemExit("graph replay disagrees with eager launches")
+    eager_ms, med = time_phases(r, args.steps)
+    ab = algorithmic_bytes(r, ctr)
+    ab_phase = {"mark+compact": ab["mark"] + ab["compact"], "entropy": ab["entropy"], "idct": ab["idct"],
+                "resolve": ab["resolve"]}
+    n_items = int(ctr[jpt.CTR_ITEMS]); n_du = n_items * 6
+    dec_ms = float(med[1] + med[2])
+    dom = PHASES[int(np.argmax(med))]
+    dom_ms = float(med[PHASES.index(dom)])
+    achieved = ab_phase[dom] / (dom_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": int(ab_phase[dom]), "avg_launch_ms": round(dom_ms, 4)}
+    out = {
+        "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms/frame", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": label, "views": r.views.n, "pixels": r.views.n_pixels,
+                   "visible_blocks": int(ctr[jpt.CTR_VISIBLE]), "decoded_blocks": int(ctr[jpt.CTR_NEW]),
+                   "data_units": n_du},
+        "gpu_ms_per_frame_median": round(float(np.median(gpu_frame)), 4),
+        "eager_ms_per_frame": round(eager_ms, 4),
+        "phases_ms_median": {n: round(float(m), 4) for n, m in zip(PHASES, med)},
+        "mblocks_per_s": round(n_du / (dec_ms * 1e-3) / 1e6, 1),
+        "hbm_gbps_algorithmic": round(ab["method"] / (float(np.median(gpu_frame)) * 1e-3) / 1e9, 1),
+        "roofline": roof,
+    }
+    return r, out
+
+
+def diff_form(args):
+    """Differentiable form: one step = forward (F -> frame) + L2 loss +
+    backward (-> dL/dF) through torch.autograd on the diff1080 scene."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    from paper_2510_08166_amd.synth import configs, target_frame
+    wl = configs.diff1080()
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, device="cuda:0")
+    r.mark()
+    jpt.entropy_decode(r.scene, r.frame)
+    diff = jpt.DiffFrame(r)
+    F = diff.dequantize()
+    g = wl.views[0]
+    tgt = torch.from_numpy(target_frame(22, *g.shape).reshape(-1, 3)).cuda()
+
+    def step():
+        Fl = F.detach().requires_grad_(True)
+        loss = ((diff(Fl) - tgt) ** 2).sum()
+        loss.backward()
+        return Fl.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fw, bw = [], []
+    dfr = torch.ones(diff.n_pixels, 3, device="cuda")
+    for _ in range(args.steps):
+        ev[0].record()
+        diff.forward(F)
+        ev[1].record()
+        diff.backward(dfr, tuple(F.shape))
+        ev[2].record()
+        torch.cuda.synchronize()
+        fw.append(ev[0].elapsed_time(ev[1])); bw.append(ev[1].elapsed_time(ev[2]))
+    n = F.shape[0]
+    return {"metric": "fwd+bwd ms (differentiable form)", "value": round(ms, 4), "unit": "ms/step", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": wl.name, "work_items": int(n), "coefficients": int(n * 384),
+                       "pixels": int(diff.n_pixels)},
+            "fwd_ms_median": round(float(np.median(fw)), 4), "bwd_ms_median": round(float(np.median(bw)), 4)}
+
+
+def calibrate_copy():
+    """One device copy of 1 GiB, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of a profiled run to bytes."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    torch.add(a, 1, out=b)  # one elementwise kernel: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    log("copy calibration: 1073741824 bytes read and written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="frame1080", choices=["frame1080", "batched16", "diff1080"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is single-GPU (each device would run the same per-frame "
               "pipeline on its share of the screen); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2510_08166_amd import jpt
     from paper_2510_08166_amd.synth import configs
-
+    if args.calibrate_copy:
+        calibrate_copy()
+    if args.workload == "diff1080":
+        print(json.dumps(diff_form(args)), flush=True)
+        return
     t0 = time.perf_counter()
-    wl = configs.frame1080()
+    if args.workload == "frame1080":
+        wl = configs.frame1080()
+        label = ("1080p: 32 x 2048^2 textures (q50-90, 4:2:0, 8 levels), 1920x1080 G-buffer from 200 quads, "
+                 "bilinear, no cache")
+    else:
+        wl = configs.batched16()
+        label = ("batched: 16 views (2 stereo pairs 2064x2208 + 12 mono 1280x720..2560x1440) over a 128-texture "
+                 "pool (512..4096, q50-90, 4:2:0), one graph launch per frame, bilinear, no cache")
     log("workload generated in %.1f s" % (time.perf_counter() - t0))
-    t0 = time.perf_counter()
-    r = jpt.Renderer(wl.textures, wl.views, wl.filter, device="cuda:0")
-    torch.cuda.synchronize()
-    log("index built and uploaded in %.1f s" % (time.perf_counter() - t0))
-
-    def step(ev=None):
-        if ev: ev[0].record()
-        r.mark()
-        if ev: ev[1].record()
-        jpt.entropy_decode(r.scene, r.frame)
-        if ev: ev[2].record()
-        jpt.idct_color(r.scene, r.frame, r.cache)
-        if ev: ev[3].record()
-        r.resolve()
-        if ev: ev[4].record()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctr = r.frame.counters_host().copy()
-    if ctr[jpt.CTR_ERROR]:
-        raise SystemExit("device error flags %x" % ctr[jpt.CTR_ERROR])
-    names = ["mark+compact", "entropy", "idct", "resolve"]
-    # (1) eager launches with events between the four C-ABI calls: per-phase GPU time
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s_ in range(args.steps):
-        step(evs[s_])
-    torch.cuda.synchronize()
-    eager_ms = 1000.0 * (time.perf_counter() - t0) / args.steps
-    ph = np.array([[evs[s_][i].elapsed_time(evs[s_][i + 1]) for i in range(4)] for s_ in range(args.steps)])
-    med = np.median(ph, axis=0)
-    phases = {n: round(float(m), 4) for n, m in zip(names, med)}
-    # (2) the same frame captured once into a HIP graph and replayed: the timed steps
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        step()
-    torch.cuda.current_stream().wait_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step()
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    gev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gev[0].record()
-    for s_ in range(args.steps):
-        graph.replay()
-        gev[s_ + 1].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1000.0 * wall / args.steps
-    gpu_frame = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(args.steps)])
-    ctr2 = r.frame.counters_host()
-    if ctr2[jpt.CTR_ERROR] or ctr2[jpt.CTR_NEW] != ctr[jpt.CTR_NEW]:
-        raise SystemExit("graph replay disagrees with eager launches")
-    ab = algorithmic_bytes(r, ctr)
-    ab_phase = {"mark+compact": ab["mark"] + ab["compact"], "entropy": ab["entropy"], "idct": ab["idct"],
-                "resolve": ab["resolve"]}
-    n_items = int(ctr[jpt.CTR_ITEMS]); n_du = n_items * 6
-    dec_ms = float(med[1] + med[2])
-    # dominant kernel and its roofline (algorithmic bytes / event-timed duration)
-    dom = names[int(np.argmax(med))]
-    dom_ms = float(med[names.index(dom)])
-    achieved = ab_phase[dom] / (dom_ms * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "algorithmic_bytes_per_launch": int(ab_phase[dom]), "avg_launch_ms": round(dom_ms, 4)}
-    out = {
-        "metric": METRIC,
-        "value": round(ms_per_step, 4),
-        "unit": "ms/frame",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": "1080p: 32 x 2048^2 textures (q50-90, 4:2:0, 8 levels), 1920x1080 G-buffer "
-                               "from 200 quads, bilinear, no cache", "pixels": r.views.n_pixels,
-                   "visible_blocks": int(ctr[jpt.CTR_VISIBLE]), "decoded_blocks": int(ctr[jpt.CTR_NEW]),
-                   "data_units": n_du},
-        "gpu_ms_per_frame_median": round(float(np.median(gpu_frame)), 4),
-        "eager_ms_per_frame": round(eager_ms, 4),
-        "phases_ms_median": phases,
-        "mblocks_per_s": round(n_du / (dec_ms * 1e-3) / 1e6, 1),
-        "hbm_gbps_algorithmic": round(ab["method"] / (float(np.median(gpu_frame)) * 1e-3) / 1e9, 1),
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
+    r, out = plain_form(args, wl, label)
+    if args.workload == "frame1080" and not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)

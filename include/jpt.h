@@ -239,8 +239,12 @@ typedef struct jpt_frame {        /* per-frame device scratch, caller-allocated 
     uint64_t *scan;               /* jpt_scan_entries(n_blocks) entries */
     int16_t *coef;                /* max_items * 6 * 64 quantised coefficients, zigzag order */
     uint32_t max_items;
-    uint32_t frame_no;            /* LRU timestamp of this frame */
+    uint32_t frame_no;            /* LRU timestamp f of this frame, or JPT_FRAME_AUTO: the cache's own
+                                     frame counter (0 after jpt_cache_reset, then one more after every
+                                     frame), so that a captured graph can be replayed frame after frame */
 } jpt_frame;
+
+#define JPT_FRAME_AUTO 0xFFFFFFFFu
 
 /* Decoded-block cache (paper: "Texture Block Cache", "Update Cache"),
  * caller-allocated.  JPT_CACHE_NONE needs texels and slot_of only; the
@@ -269,11 +273,20 @@ typedef struct jpt_cache {
  * `stream`.  Errors: JPT_E_ARG, JPT_E_HIP. */
 jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, void *stream);
 
-typedef struct jpt_tuning {       /* launch knobs; NULL = defaults */
-    uint32_t decode_groups;       /* persistent workgroups of the decode kernels (0 = auto) */
+typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results never depend on them. */
+    uint32_t decode_groups;       /* persistent workgroups of the entropy decoder (0 = auto) */
     uint32_t idct_groups;         /* persistent workgroups of the IDCT kernel (0 = auto) */
-    uint32_t reserved[6];
+    uint32_t mark_groups;         /* workgroups of the mark kernel (0 = one per pixel tile; else each
+                                     walks the tiles of all views with that stride) */
+    uint32_t resolve_groups;      /* the same for the resolve kernel */
+    uint32_t flags;               /* JPT_TUNE_* */
+    uint32_t reserved[3];
 } jpt_tuning;
+
+/* jpt_tuning.flags: hand each of the GPU's 8 chiplets (XCDs, each with its
+ * own L2) a contiguous run of pixel tiles in mark and resolve, instead of
+ * interleaving neighbouring tiles over all of them. */
+#define JPT_TUNE_XCD_TILES 1u
 
 /* Entries of jpt_frame.scan for a scene of n_blocks block ids (two scans
  * of the block bitmask per frame). */
@@ -330,6 +343,29 @@ jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n
                        const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
 
 /* ------------------------------------------------------------------ *
+ * Batched form: one frame over all views (jpt_mark_blocks, then
+ * jpt_decode_blocks, then jpt_resolve, each with the arguments given here)
+ * captured into a HIP graph, so that a frame of any number of views is one
+ * graph launch.  The argument structs are copied at capture; the device
+ * buffers they point to must outlive the graph, and every replay reads the
+ * G-buffers and rewrites the frames in place.  With JPT_CACHE_LRU use
+ * frame->frame_no = JPT_FRAME_AUTO, or every replay reuses the captured
+ * frame number.  `stream` must not be the null stream.  The handle is
+ * host memory owned by the library until jpt_graph_destroy.
+ * ------------------------------------------------------------------ */
+typedef struct jpt_graph jpt_graph;
+
+/* Errors: JPT_E_ARG (also: stream already capturing), the errors of the
+ * captured calls, JPT_E_HIP. */
+jpt_status jpt_graph_capture(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                             jpt_frame *frame, jpt_cache *cache, uint32_t idct_mode, const jpt_tuning *tuning,
+                             void *stream, jpt_graph **out);
+/* Enqueue one frame on `stream`.  Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_graph_launch(jpt_graph *graph, void *stream);
+/* Free the graph (NULL is a no-op).  Errors: JPT_E_HIP. */
+jpt_status jpt_graph_destroy(jpt_graph *graph);
+
+/* ------------------------------------------------------------------ *
  * Differentiable form.  The frame as a function of the dequantised DCT
  * coefficients of this frame's work items (paper: Decode, whose stages are
  * dequantisation, the 8x8 IDCT and the colour transform, followed by the
@@ -343,9 +379,11 @@ jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n
  *   constant.
  * Requires every block the views read to be a work item of the last
  * jpt_mark_blocks (JPT_CACHE_NONE with n_slots >= the visible blocks).
- * F and dF: max_items x 6 x 64 floats, natural order (index v*8+u, v the
- * vertical frequency), one 64-entry unit per data unit of the item (4:2:0:
- * Y0..Y3, Cb, Cr; 4:4:4: Y, Cb, Cr, then three zero units).
+ * F and dF: n_rows x 6 x 64 floats, natural order (index v*8+u, v the
+ * vertical frequency), row i for work item i, one 64-entry unit per data
+ * unit of the item (4:2:0: Y0..Y3, Cb, Cr; 4:4:4: Y, Cb, Cr, then three zero
+ * units).  Only the first min(items listed, max_items, n_rows) rows are read
+ * or written: n_rows should be counters[JPT_CTR_ITEMS] of the frame.
  * texel_f: n_slots x 16 x 16 x 3 floats.  frame_f / dframe: the views'
  * pixels in order, width x height x 3 floats each, packed.  All pointers
  * are device memory owned by the caller; calls are asynchronous on `stream`.
@@ -353,15 +391,15 @@ jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n
 
 /* F = coefficient x quantiser for the listed work items (from frame->coef).
  * Errors: JPT_E_ARG, JPT_E_HIP. */
-jpt_status jpt_dequantize(const jpt_scene *scene, const jpt_frame *frame, float *F, void *stream);
+jpt_status jpt_dequantize(const jpt_scene *scene, const jpt_frame *frame, float *F, uint32_t n_rows, void *stream);
 
 /* Forward: F -> texel_f (the work items' texels) -> frame_f.  Invalid
  * pixels and taps in blocks without a slot raise JPT_ERR_PIXEL in
  * frame->counters; background pixels get 0.
  * Errors: JPT_E_ARG, JPT_E_HIP. */
 jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
-                         const jpt_frame *frame, const jpt_cache *cache, const float *F, float *texel_f,
-                         float *frame_f, void *stream);
+                         const jpt_frame *frame, const jpt_cache *cache, const float *F, uint32_t n_rows,
+                         float *texel_f, float *frame_f, void *stream);
 
 /* Backward: dframe = dL/dframe_f -> dF = dL/dF.  dtexel is scratch of
  * n_slots x 768 int64 (texel gradients in fixed point, 2^-32 units, summed
@@ -369,7 +407,7 @@ jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t
  * Errors: JPT_E_ARG, JPT_E_HIP. */
 jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                         const jpt_frame *frame, const jpt_cache *cache, const float *dframe, int64_t *dtexel,
-                        float *dF, void *stream);
+                        float *dF, uint32_t n_rows, void *stream);
 
 uint32_t jpt_version(void);
 const char *jpt_status_string(jpt_status s);

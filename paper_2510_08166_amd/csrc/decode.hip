@@ -470,6 +470,102 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
     }
 }
 
+// Separable fp32 IDCT on the vector ALUs, one wave per work item: a row pass
+// T[v][x] = sum_u F[v][u] P[u][x] and a column pass S[y][x] = sum_v P[v][y]
+// T[v][x], lane = (data unit, row); then the same sample clamp, colour
+// conversion and store as k_idct_mfma.
+__global__ __launch_bounds__(64) void k_idct_scalar(const jpt_level_desc *__restrict__ levels,
+                                                    const uint32_t *__restrict__ word_level,
+                                                    const uint16_t *__restrict__ quant,
+                                                    const uint32_t *__restrict__ work,
+                                                    const uint32_t *__restrict__ counters,
+                                                    const int16_t *__restrict__ coef,
+                                                    const uint32_t *__restrict__ slot_of,
+                                                    uint32_t *__restrict__ texels) {
+    __shared__ float s_P[64];
+    __shared__ float s_F[kItemCoefs];
+    __shared__ float s_T[kItemCoefs];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t n_items = counters[JPT_CTR_ITEMS];
+    s_P[lane] = basis1d((int)(lane >> 3), (int)(lane & 7));
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint32_t w = work[it];
+        const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
+        const jpt_level_desc *L = levels + word_level[b >> 5];
+        const uint32_t slot = slot_of[b];
+        const bool s444 = L->sampling == JPT_SAMPLING_444;
+        bool present = true;
+        if (s444) {
+            const uint32_t r = b - L->blk_base, by = r / L->blk_cols, bx = r - by * L->blk_cols;
+            present = 2 * bx + (q & 1) < L->mcu_cols && 2 * by + (q >> 1) < L->n_mcu / L->mcu_cols;
+        }
+        if (slot == JPT_SLOT_NONE || !present) continue;  // uniform over the wave
+        const bool failed = w >> 31;
+        uint32_t *dst = texels + (size_t)slot * 256;
+        if (failed) {
+            if (!s444) {
+                for (uint32_t i = lane; i < 256; i += 64) dst[i] = JPT_TEXEL_INVALID;
+            } else {
+                dst[(8 * (q >> 1) + (lane >> 3)) * 16 + 8 * (q & 1) + (lane & 7)] = JPT_TEXEL_INVALID;
+            }
+            continue;
+        }
+        const int ndu = s444 ? 3 : 6;
+        const uint16_t *qt = quant + (size_t)L->quant * 128;
+        for (int i = (int)lane; i < ndu * 64; i += 64) {
+            const int du = i >> 6, k = i & 63;
+            const int comp = s444 ? du : (du < 4 ? 0 : 1);
+            s_F[du * 64 + kZigZag.nat[k]] =
+                (float)((int)coef[(size_t)it * kItemCoefs + i] * (int)qt[(comp ? 64 : 0) + k]);
+        }
+        __syncthreads();
+        const uint32_t du = lane >> 3, rr = lane & 7;
+        if ((int)du < ndu) {
+            float o[8];
+#pragma unroll
+            for (int x = 0; x < 8; x++) o[x] = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const float f = s_F[du * 64 + rr * 8 + u];
+#pragma unroll
+                for (int x = 0; x < 8; x++) o[x] += f * s_P[u * 8 + x];
+            }
+#pragma unroll
+            for (int x = 0; x < 8; x++) s_T[du * 64 + rr * 8 + x] = o[x];
+        }
+        __syncthreads();
+        if ((int)du < ndu) {
+            float o[8];
+#pragma unroll
+            for (int y = 0; y < 8; y++) o[y] = 0.0f;
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                const float t = s_T[du * 64 + v * 8 + rr];  // column rr
+#pragma unroll
+                for (int y = 0; y < 8; y++) o[y] += s_P[v * 8 + y] * t;
+            }
+#pragma unroll
+            for (int y = 0; y < 8; y++) s_F[du * 64 + y * 8 + rr] = fminf(fmaxf(o[y] + 128.0f, 0.0f), 255.0f);
+        }
+        __syncthreads();
+        if (!s444) {
+            const uint32_t ty = lane >> 2, tx0 = (lane & 3) * 4;
+            uint32_t o[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t tx = tx0 + i;
+                o[i] = ycc_to_rgba(s_F[((ty >> 3) * 2 + (tx >> 3)) * 64 + (ty & 7) * 8 + (tx & 7)],
+                                   s_F[4 * 64 + (ty >> 1) * 8 + (tx >> 1)], s_F[5 * 64 + (ty >> 1) * 8 + (tx >> 1)]);
+            }
+            *reinterpret_cast<uint4 *>(dst + ty * 16 + tx0) = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+            dst[(8 * (q >> 1) + (lane >> 3)) * 16 + 8 * (q & 1) + (lane & 7)] =
+                ycc_to_rgba(s_F[lane], s_F[64 + lane], s_F[128 + lane]);
+        }
+        __syncthreads();
+    }
+}
+
 uint32_t default_groups(const jpt_tuning *t, bool idct) {
     uint32_t g = t ? (idct ? t->idct_groups : t->decode_groups) : 0u;
     return g ? g : (idct ? 2048u : 512u);
@@ -509,10 +605,16 @@ extern "C" jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, j
     jpt_status s = check_args(scene, frame);
     if (s) return s;
     if (!cache || !cache->texels || !cache->slot_of) return JPT_E_ARG;
-    if (idct_mode != JPT_IDCT_MFMA_F16) return JPT_E_ARG;
-    hipLaunchKernelGGL(k_idct_mfma, dim3(default_groups(tuning, true)), dim3(64), 0, (hipStream_t)stream,
-                       scene->levels, scene->word_level, scene->quant, frame->work, frame->counters, frame->coef,
-                       cache->slot_of, cache->texels);
+    if (idct_mode == JPT_IDCT_MFMA_F16)
+        hipLaunchKernelGGL(k_idct_mfma, dim3(default_groups(tuning, true)), dim3(64), 0, (hipStream_t)stream,
+                           scene->levels, scene->word_level, scene->quant, frame->work, frame->counters, frame->coef,
+                           cache->slot_of, cache->texels);
+    else if (idct_mode == JPT_IDCT_SCALAR_F32)
+        hipLaunchKernelGGL(k_idct_scalar, dim3(4 * default_groups(tuning, true)), dim3(64), 0, (hipStream_t)stream,
+                           scene->levels, scene->word_level, scene->quant, frame->work, frame->counters, frame->coef,
+                           cache->slot_of, cache->texels);
+    else
+        return JPT_E_ARG;
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }
@@ -522,7 +624,7 @@ extern "C" jpt_status jpt_decode_blocks(const jpt_scene *scene, jpt_frame *frame
     jpt_status s = check_args(scene, frame);
     if (s) return s;
     if (!cache || !cache->texels || !cache->slot_of) return JPT_E_ARG;
-    if (idct_mode != JPT_IDCT_MFMA_F16) return JPT_E_ARG;
+    if (idct_mode != JPT_IDCT_MFMA_F16 && idct_mode != JPT_IDCT_SCALAR_F32) return JPT_E_ARG;
     if ((s = launch_entropy(scene, frame, tuning, (hipStream_t)stream))) return s;
     return jpt_idct_color(scene, frame, cache, idct_mode, tuning, stream);
 }

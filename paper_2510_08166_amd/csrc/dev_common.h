@@ -144,6 +144,67 @@ JPT_DEV uint32_t block_of(const LevelFoot &F, uint32_t x, uint32_t y) {
     return F.blk_base + (y >> 4) * F.blk_cols + (x >> 4);
 }
 
+// ------------------------------------------------------------ view tables
+// One launch of mark or resolve covers the pixel tiles of up to
+// kMaxLaunchViews views.  Tiles are numbered view by view, row-major inside
+// a view.  With `xcd_chunk` set, launch slot s (workgroup s, or its k-th
+// step in a strided loop with a stride that is a multiple of 8) serves tile
+// (s % 8) * xcd_chunk + s / 8: the hardware deals workgroups to the 8 XCDs
+// round-robin, so each XCD (and its L2) gets a contiguous run of tiles.
+constexpr uint32_t kMaxLaunchViews = 16;
+
+struct LaunchView {
+    const jpt_gpixel *gbuf;
+    uint32_t *frame;
+    uint32_t width, height, pitch, frame_pitch;
+    uint32_t tiles_x, tile_end;  // tiles per row; first tile of the next view
+};
+
+struct ViewTable {
+    uint32_t n, total;  // views, tiles
+    uint32_t span;      // launch slots: total, or 8 * xcd_chunk
+    uint32_t xcd_chunk;
+    LaunchView v[kMaxLaunchViews];
+};
+
+// Tile of launch slot `s`: view, tile column and row.  False for a padding
+// slot.  The view search ends at the last view with tiles (tile_end = total).
+JPT_DEV bool tile_of(const ViewTable &T, uint32_t s, uint32_t &view, uint32_t &tx, uint32_t &ty) {
+    const uint32_t t = T.xcd_chunk ? (s & 7u) * T.xcd_chunk + (s >> 3) : s;
+    if (t >= T.total) return false;
+    uint32_t v = 0;
+    while (t >= T.v[v].tile_end) v++;
+    const uint32_t lt = t - (v ? T.v[v - 1].tile_end : 0u);
+    ty = lt / T.v[v].tiles_x;
+    tx = lt - ty * T.v[v].tiles_x;
+    view = v;
+    return true;
+}
+
+// Host side: fill a table with views [first, first + n) (n <= kMaxLaunchViews)
+// for tiles of tw x th pixels; views without pixels get no tiles.
+inline void make_view_table(const jpt_view *views, uint32_t first, uint32_t n, uint32_t tw, uint32_t th, bool xcd,
+                            ViewTable &T) {
+    T.n = n;
+    uint32_t total = 0;
+    for (uint32_t i = 0; i < kMaxLaunchViews; i++) {
+        LaunchView &L = T.v[i];
+        if (i < n) {
+            const jpt_view &V = views[first + i];
+            L.gbuf = V.gbuf; L.frame = V.frame;
+            L.width = V.width; L.height = V.height; L.pitch = V.pitch; L.frame_pitch = V.frame_pitch;
+            L.tiles_x = (V.width + tw - 1) / tw;
+            total += (V.width && V.height) ? L.tiles_x * ((V.height + th - 1) / th) : 0u;
+        } else {
+            L = LaunchView{nullptr, nullptr, 0, 0, 0, 0, 1, 0};
+        }
+        L.tile_end = total;
+    }
+    T.total = total;
+    T.xcd_chunk = xcd ? (total + 7) / 8 : 0u;
+    T.span = xcd ? 8 * T.xcd_chunk : total;
+}
+
 #define HIP_CHECK_LAUNCH()                                   \
     do {                                                     \
         if (hipGetLastError() != hipSuccess) return JPT_E_HIP; \

@@ -81,9 +81,10 @@ __global__ __launch_bounds__(256) void k_dequant(const jpt_level_desc *__restric
                                                  const uint32_t *__restrict__ counters,
                                                  const int16_t *__restrict__ coef, float *__restrict__ F,
                                                  uint32_t max_items) {
-    const uint32_t n_items = min(counters[JPT_CTR_ITEMS], max_items);
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n_items * kItemCoefs; i += gridDim.x * 256) {
-        const uint32_t it = i / kItemCoefs, r = i - it * kItemCoefs, du = r >> 6, k = r & 63;  // k: zigzag position
+    const uint64_t n = (uint64_t)min(counters[JPT_CTR_ITEMS], max_items) * kItemCoefs;
+    for (uint64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint32_t it = (uint32_t)(i / kItemCoefs), r = (uint32_t)(i - (uint64_t)it * kItemCoefs);
+        const uint32_t du = r >> 6, k = r & 63;  // k: zigzag position
         const uint32_t b = (work[it] & 0x7FFFFFFFu) >> 2;
         const jpt_level_desc *L = levels + word_level[b >> 5];
         const bool s444 = L->sampling == JPT_SAMPLING_444;
@@ -346,25 +347,28 @@ jpt_status check(const jpt_scene *scene, const jpt_view *views, uint32_t n_views
 
 }  // namespace
 
-extern "C" jpt_status jpt_dequantize(const jpt_scene *scene, const jpt_frame *frame, float *F, void *stream) {
+static uint32_t row_limit(const jpt_frame *frame, uint32_t n_rows) { return n_rows < frame->max_items ? n_rows : frame->max_items; }
+
+extern "C" jpt_status jpt_dequantize(const jpt_scene *scene, const jpt_frame *frame, float *F, uint32_t n_rows,
+                                     void *stream) {
     if (!scene || !frame || !F || !scene->levels || !scene->word_level || !scene->quant || !frame->work ||
         !frame->counters || !frame->coef)
         return JPT_E_ARG;
     hipLaunchKernelGGL(k_dequant, dim3(1024), dim3(256), 0, (hipStream_t)stream, scene->levels, scene->word_level,
-                       scene->quant, frame->work, frame->counters, frame->coef, F, frame->max_items);
+                       scene->quant, frame->work, frame->counters, frame->coef, F, row_limit(frame, n_rows));
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }
 
 extern "C" jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
-                                    const jpt_frame *frame, const jpt_cache *cache, const float *F, float *texel_f,
-                                    float *frame_f, void *stream) {
+                                    const jpt_frame *frame, const jpt_cache *cache, const float *F, uint32_t n_rows,
+                                    float *texel_f, float *frame_f, void *stream) {
     jpt_status s = check(scene, views, n_views, filter, frame, cache);
     if (s) return s;
     if (!F || !texel_f || !frame_f) return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_fwd_texels, dim3(4096), dim3(64), 0, st, scene->levels, scene->word_level, frame->work,
-                       frame->counters, cache->slot_of, F, texel_f, frame->max_items);
+                       frame->counters, cache->slot_of, F, texel_f, row_limit(frame, n_rows));
     HIP_CHECK_LAUNCH();
     size_t off = 0;
     for (uint32_t v = 0; v < n_views; v++) {
@@ -387,7 +391,7 @@ extern "C" jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *view
 
 extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                                    const jpt_frame *frame, const jpt_cache *cache, const float *dframe,
-                                   int64_t *dtexel, float *dF, void *stream) {
+                                   int64_t *dtexel, float *dF, uint32_t n_rows, void *stream) {
     jpt_status s = check(scene, views, n_views, filter, frame, cache);
     if (s) return s;
     if (!dframe || !dtexel || !dF || cache->n_slots == 0) return JPT_E_ARG;
@@ -412,7 +416,7 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
         off += (size_t)V.width * V.height * 3;
     }
     hipLaunchKernelGGL(k_bwd_texels, dim3(4096), dim3(64), 0, st, scene->levels, scene->word_level, frame->work,
-                       frame->counters, cache->slot_of, dt, dF, frame->max_items);
+                       frame->counters, cache->slot_of, dt, dF, row_limit(frame, n_rows));
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }

@@ -44,4 +44,5 @@
 #define JPT_META_ABIN 3       // age bin of the last evicted blocks
 #define JPT_META_TIES 4       // blocks of that bin to evict (smallest ids)
 #define JPT_META_EVICTED 5    // evicted this frame
+#define JPT_META_FRAME 6      // frame number of the next frame (JPT_FRAME_AUTO)
 #define JPT_META_HIST 16      // JPT_LRU_MAX_AGE + 1 bins

@@ -43,11 +43,12 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
     atomicOr(vis + word, bit);  // set crowded: go straight to HBM
 }
 
+// One workgroup marks one 64 x 32 pixel tile per step and walks the tiles of
+// every view in the launch's table with a stride of gridDim.x.
 template <bool kLdsDesc>
 __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
-                                                       uint32_t n_lev, const jpt_gpixel *__restrict__ gbuf,
-                                                       uint32_t W, uint32_t H, uint32_t pitch, uint32_t filter,
+                                                       uint32_t n_lev, const ViewTable tab, uint32_t filter,
                                                        uint32_t *__restrict__ vis, uint32_t *__restrict__ counters) {
     constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize];
@@ -55,76 +56,89 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
     __shared__ uint32_t s_bad;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t x = blockIdx.x * kTileW + lane;
-    // all of this lane's G-buffer pixels in flight at once (rows wv, wv+4, ...)
-    jpt_gpixel px[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-        const uint32_t y = blockIdx.y * kTileH + wv + r * (kMarkThreads / 64);
-        px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
-    }
-    for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
-        s_key[i] = 0xFFFFFFFFu;
-        s_bits[i] = 0;
-    }
     if (threadIdx.x == 0) s_bad = 0;
     if constexpr (kLdsDesc) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
-    __syncthreads();
     bool invalid = false;
+    for (uint32_t slot = blockIdx.x; slot < tab.span; slot += gridDim.x) {
+        uint32_t view, tx, ty;
+        if (!tile_of(tab, slot, view, tx, ty)) continue;  // uniform over the workgroup
+        const jpt_gpixel *__restrict__ gbuf = tab.v[view].gbuf;
+        const uint32_t W = tab.v[view].width, H = tab.v[view].height, pitch = tab.v[view].pitch;
+        const uint32_t x = tx * kTileW + lane;
+        // all of this lane's G-buffer pixels in flight at once (rows wv, wv+4, ...)
+        jpt_gpixel px[kRows];
 #pragma unroll
-    for (int r = 0; r < kRows; r++) {
-        uint32_t ids[8];
+        for (int r = 0; r < kRows; r++) {
+            const uint32_t y = ty * kTileH + wv + r * (kMarkThreads / 64);
+            px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+        }
+        for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
+            s_key[i] = 0xFFFFFFFFu;
+            s_bits[i] = 0;
+        }
+        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 8; k++) ids[k] = 0xFFFFFFFFu;
-        LevelFoot foot[2];
-        int nf;
-        uint32_t tw;
-        int st;
-        if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px[r], filter, foot, nf, tw);
-        else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px[r], filter, foot, nf, tw);
-        if (st == PIX_INVALID) {
-            invalid = true;
-        } else if (st == PIX_VALID) {
+        for (int r = 0; r < kRows; r++) {
+            uint32_t ids[8];
 #pragma unroll
-            for (int k = 0; k < 2; k++) {
-                if (k >= nf || foot[k].lw == 0) continue;
-                const LevelFoot &F = foot[k];
-                if (filter == JPT_FILTER_NEAREST) {
-                    ids[4 * k] = block_of(F, F.x0, F.y0);
-                } else {
-                    const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
-                    if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
-                    if (c1 && r0) ids[4 * k + 1] = block_of(F, F.x1, F.y0);
-                    if (c0 && r1) ids[4 * k + 2] = block_of(F, F.x0, F.y1);
-                    if (c1 && r1) ids[4 * k + 3] = block_of(F, F.x1, F.y1);
+            for (int k = 0; k < 8; k++) ids[k] = 0xFFFFFFFFu;
+            LevelFoot foot[2];
+            int nf;
+            uint32_t tw;
+            int st;
+            if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px[r], filter, foot, nf, tw);
+            else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px[r], filter, foot, nf, tw);
+            if (st == PIX_INVALID) {
+                invalid = true;
+            } else if (st == PIX_VALID) {
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    if (k >= nf || foot[k].lw == 0) continue;
+                    const LevelFoot &F = foot[k];
+                    if (filter == JPT_FILTER_NEAREST) {
+                        ids[4 * k] = block_of(F, F.x0, F.y0);
+                    } else {
+                        const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
+                        if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
+                        if (c1 && r0) ids[4 * k + 1] = block_of(F, F.x1, F.y0);
+                        if (c0 && r1) ids[4 * k + 2] = block_of(F, F.x0, F.y1);
+                        if (c1 && r1) ids[4 * k + 3] = block_of(F, F.x1, F.y1);
+                    }
                 }
             }
-        }
-        // Distinct ids of the wave: take the first pending id of the first
-        // lane that has one, drop it everywhere, let that lane record it.
-        while (true) {
-            uint32_t cand = 0xFFFFFFFFu;
+            // Distinct ids of the wave: take the first pending id of the first
+            // lane that has one, drop it everywhere, let that lane record it.
+            while (true) {
+                uint32_t cand = 0xFFFFFFFFu;
 #pragma unroll
-            for (int k = 7; k >= 0; k--)
-                if (ids[k] != 0xFFFFFFFFu) cand = ids[k];
-            const uint64_t pending = __ballot(cand != 0xFFFFFFFFu);
-            if (pending == 0) break;
-            const int leader = __builtin_ctzll(pending);
-            const uint32_t id = __builtin_amdgcn_readlane(cand, leader);
+                for (int k = 7; k >= 0; k--)
+                    if (ids[k] != 0xFFFFFFFFu) cand = ids[k];
+                const uint64_t pending = __ballot(cand != 0xFFFFFFFFu);
+                if (pending == 0) break;
+                const int leader = __builtin_ctzll(pending);
+                const uint32_t id = __builtin_amdgcn_readlane(cand, leader);
 #pragma unroll
-            for (int k = 0; k < 8; k++)
-                if (ids[k] == id) ids[k] = 0xFFFFFFFFu;
-            if ((int)lane == leader) set_insert(s_key, s_bits, vis, id);
+                for (int k = 0; k < 8; k++)
+                    if (ids[k] == id) ids[k] = 0xFFFFFFFFu;
+                if ((int)lane == leader) set_insert(s_key, s_bits, vis, id);
+            }
         }
+        __syncthreads();
+        // one HBM atomic per distinct bitmask word of the tile
+        for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
+            const uint32_t k = s_key[i];
+            if (k != 0xFFFFFFFFu) atomicOr(vis + k, s_bits[i]);
+        }
+        __syncthreads();  // the set is reused by the next tile
     }
     if (__ballot(invalid) && lane == 0) atomicOr(&s_bad, 1u);
     __syncthreads();
-    // one HBM atomic per distinct bitmask word of the tile
-    for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
-        const uint32_t k = s_key[i];
-        if (k != 0xFFFFFFFFu) atomicOr(vis + k, s_bits[i]);
-    }
     if (threadIdx.x == 0 && s_bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
+}
+
+// Frame number of an LRU frame: the caller's, or the cache's own counter.
+__device__ __forceinline__ uint32_t lru_frame(uint32_t frame_no, const uint32_t *__restrict__ meta) {
+    return frame_no != JPT_FRAME_AUTO ? frame_no : meta[JPT_META_FRAME];
 }
 
 // ---------------------------------------------------------- compaction
@@ -225,12 +239,14 @@ __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restri
                                                         uint64_t *__restrict__ tile_sums,
                                                         uint32_t *__restrict__ counters,
                                                         const uint32_t *__restrict__ slot_of,
-                                                        uint32_t *__restrict__ last_used, uint32_t frame_no) {
+                                                        uint32_t *__restrict__ last_used, uint32_t frame_no,
+                                                        const uint32_t *__restrict__ meta) {
     WordCounts wc;
     uint32_t nv;
     const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
     const uint64_t s = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
     if (resident) {
+        const uint32_t f = lru_frame(frame_no, meta);
 #pragma unroll
         for (int i = 0; i < kWpt; i++) {
             if (w0 + i >= n_words) continue;
@@ -238,7 +254,7 @@ __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restri
             while (m) {
                 const uint32_t b = (w0 + i) * 32 + __builtin_ctz(m);
                 m &= m - 1;
-                last_used[slot_of[b]] = frame_no;
+                last_used[slot_of[b]] = f;
             }
         }
     }
@@ -266,6 +282,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
     const uint64_t mine = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
     const uint64_t base = scan_base(tile_sums, mine);
     const uint32_t top = kLru ? meta[JPT_META_TOP] : 0u;  // free slots after this frame's evictions
+    const uint32_t f = kLru ? lru_frame(frame_no, meta) : 0u;
     uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
     bool overflow = false;
 #pragma unroll
@@ -285,7 +302,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
                 if (blk < top && fits) {
                     slot = free_stack[top - 1 - blk];
                     owner[slot] = b;
-                    last_used[slot] = frame_no;
+                    last_used[slot] = f;
                     placed |= 1u << bit;
                 }
                 overflow |= !fits || blk >= top;
@@ -354,12 +371,13 @@ __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ o
                                                   uint32_t frame_no, uint32_t *__restrict__ meta) {
     __shared__ uint32_t s_h[kAgeBins];
     if (meta[JPT_META_NEED] == 0) return;
+    const uint32_t f = lru_frame(frame_no, meta);
     for (int k = threadIdx.x; k < kAgeBins; k += 256) s_h[k] = 0;
     __syncthreads();
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
         const uint32_t b = owner[s];
         if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
-        atomicAdd(s_h + age_bin(frame_no, last_used[s]), 1u);
+        atomicAdd(s_h + age_bin(f, last_used[s]), 1u);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kAgeBins; k += 256)
@@ -420,10 +438,11 @@ __global__ __launch_bounds__(256) void k_lru_evict(uint32_t *__restrict__ owner,
                                                    uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta) {
     if (meta[JPT_META_NEED] == 0) return;
     const uint32_t abin = meta[JPT_META_ABIN], all = meta[JPT_META_TIES] == 0xFFFFFFFFu;
+    const uint32_t f = lru_frame(frame_no, meta);
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
         const uint32_t b = owner[s];
         if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
-        const uint32_t bin = age_bin(frame_no, last_used[s]);
+        const uint32_t bin = age_bin(f, last_used[s]);
         if (bin > abin || all) evict(s, b, owner, slot_of, resident, free_stack, meta);
         else if (bin == abin) atomicOr(tie_mask + (b >> 5), 1u << (b & 31));
     }
@@ -473,8 +492,10 @@ __global__ __launch_bounds__(kScanThreads) void k_tie_pick(const uint32_t *__res
 }
 
 // Pop the placed blocks off the free stack; report the update.
-__global__ void k_lru_finish(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters, uint32_t n_slots) {
+__global__ void k_lru_finish(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters, uint32_t n_slots,
+                             uint32_t frame_no) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    meta[JPT_META_FRAME] = lru_frame(frame_no, meta) + 1u;
     const uint32_t top = meta[JPT_META_TOP], n_new = meta[JPT_META_NEW];
     const uint32_t top2 = n_new < top ? top - n_new : 0u;
     meta[JPT_META_TOP] = top2;
@@ -527,7 +548,6 @@ extern "C" jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, 
 
 extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                                       jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
-    (void)tuning;
     if (!scene || !frame || (n_views && !views)) return JPT_E_ARG;
     if (filter > JPT_FILTER_TRILINEAR) return JPT_E_ARG;
     if (!scene->levels || !scene->textures || !scene->word_level || scene->n_blocks == 0 ||
@@ -552,24 +572,29 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
                            n_words, cache->meta);
         HIP_CHECK_LAUNCH();
     }
-    for (uint32_t v = 0; v < n_views; v++) {
-        const jpt_view &V = views[v];
-        if (V.width == 0 || V.height == 0) continue;
-        dim3 grid((V.width + kTileW - 1) / kTileW, (V.height + kTileH - 1) / kTileH);
-        if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
-            hipLaunchKernelGGL(k_mark<true>, grid, dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
-                               scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
-                               frame->vis, frame->counters);
+    const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
+    const bool lds_desc = scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap;
+    for (uint32_t v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
+        ViewTable tab;
+        make_view_table(views, v0, n_views - v0 < kMaxLaunchViews ? n_views - v0 : kMaxLaunchViews, kTileW, kTileH,
+                        xcd, tab);
+        if (tab.total == 0) continue;
+        uint32_t groups = tab.span;
+        if (tuning && tuning->mark_groups && tuning->mark_groups < groups)
+            groups = xcd ? (tuning->mark_groups + 7) / 8 * 8 : tuning->mark_groups;
+        if (lds_desc)
+            hipLaunchKernelGGL(k_mark<true>, dim3(groups), dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
+                               scene->n_textures, scene->n_levels, tab, filter, frame->vis, frame->counters);
         else
-            hipLaunchKernelGGL(k_mark<false>, grid, dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
-                               scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
-                               frame->vis, frame->counters);
+            hipLaunchKernelGGL(k_mark<false>, dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
+                               scene->textures, scene->n_textures, scene->n_levels, tab, filter, frame->vis,
+                               frame->counters);
         HIP_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis,
                        lru ? cache->resident : (const uint32_t *)nullptr, scene->word_level, scene->levels, n_words,
                        frame->scan, frame->counters, lru ? cache->slot_of : (const uint32_t *)nullptr,
-                       lru ? cache->last_used : (uint32_t *)nullptr, f);
+                       lru ? cache->last_used : (uint32_t *)nullptr, f, lru ? cache->meta : (const uint32_t *)nullptr);
     HIP_CHECK_LAUNCH();
     if (lru) {
         const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
@@ -589,7 +614,7 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
                            scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
                            frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
                            cache->meta, cache->owner, cache->last_used, f);
-        hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots);
+        hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f);
     } else {
         hipLaunchKernelGGL(k_emit<false>, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, (uint32_t *)nullptr,
                            scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,

@@ -3,7 +3,8 @@
 // Every tap a pixel reads was marked, so no clamping at undecoded MCU borders
 // is needed (the footprint marking makes the result exact).
 //
-// A workgroup shades a 64 x 16 pixel tile, 4 rows per lane.  The scene's
+// A workgroup shades 64 x 16 pixel tiles, 4 rows per lane, walking the
+// tiles of every view in the launch's table with a stride of gridDim.x.  The scene's
 // sampling descriptors are cached in LDS, and for each lane all tap slot
 // lookups are issued before any texel load, and all texel loads before any
 // blend, so that a lane keeps up to 32 independent loads in flight.
@@ -67,92 +68,95 @@ __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const j
 template <uint32_t kFilter, bool kLdsDesc>
 __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__restrict__ levels,
                                                       const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
-                                                      uint32_t n_lev, const jpt_gpixel *__restrict__ gbuf,
-                                                      uint32_t W, uint32_t H, uint32_t pitch,
+                                                      uint32_t n_lev, const ViewTable tab,
                                                       const uint32_t *__restrict__ slot_of,
-                                                      const uint32_t *__restrict__ texels,
-                                                      uint32_t *__restrict__ frame, uint32_t frame_pitch) {
+                                                      const uint32_t *__restrict__ texels) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
     __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t x = blockIdx.x * kTileW + lane;
-    jpt_gpixel px[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; r++) {
-        const uint32_t y = blockIdx.y * kTileH + wv + r * (kThreads / 64);
-        px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
-    }
     if constexpr (kLdsDesc) {
         load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
         __syncthreads();
     }
-    for (int r = 0; r < kRows; r++) {
-        const uint32_t y = blockIdx.y * kTileH + wv + r * (kThreads / 64);
-        Taps<kTaps> T;
-        uint32_t tw;
-        int nf, st;
-        if constexpr (kLdsDesc) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
-        else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
-        // all slot lookups of the pixel, then all texel loads
-        uint32_t slot[kTaps], tex[kTaps];
+    for (uint32_t tslot = blockIdx.x; tslot < tab.span; tslot += gridDim.x) {
+        uint32_t view, tx, ty;
+        if (!tile_of(tab, tslot, view, tx, ty)) continue;
+        const jpt_gpixel *__restrict__ gbuf = tab.v[view].gbuf;
+        uint32_t *__restrict__ frame = tab.v[view].frame;
+        const uint32_t W = tab.v[view].width, H = tab.v[view].height, pitch = tab.v[view].pitch;
+        const uint32_t frame_pitch = tab.v[view].frame_pitch;
+        const uint32_t x = tx * kTileW + lane;
+        jpt_gpixel px[kRows];
 #pragma unroll
-        for (int t = 0; t < kTaps; t++) slot[t] = T.w[t] ? slot_of[T.blk[t]] : 0u;
+        for (int r = 0; r < kRows; r++) {
+            const uint32_t y = ty * kTileH + wv + r * (kThreads / 64);
+            px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+        }
+        for (int r = 0; r < kRows; r++) {
+            const uint32_t y = ty * kTileH + wv + r * (kThreads / 64);
+            Taps<kTaps> T;
+            uint32_t tw;
+            int nf, st;
+            if constexpr (kLdsDesc) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
+            else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
+            // all slot lookups of the pixel, then all texel loads
+            uint32_t slot[kTaps], tex[kTaps];
 #pragma unroll
-        for (int t = 0; t < kTaps; t++)
-            tex[t] = (T.w[t] && slot[t] != JPT_SLOT_NONE) ? texels[(size_t)slot[t] * 256 + T.off[t]] : 0u;
-        if (x >= W || y >= H) continue;
-        uint32_t out;
-        if (st == PIX_BACKGROUND) {
-            out = 0;
-        } else if (st == PIX_INVALID) {
-            out = JPT_TEXEL_INVALID;
-        } else {
-            bool missing = false;
-            uint32_t lvl[2][3] = {{0, 0, 0}, {0, 0, 0}};
-            constexpr int kLevels = kTaps == 8 ? 2 : 1, kPer = kTaps == 1 ? 1 : 4;
+            for (int t = 0; t < kTaps; t++) slot[t] = T.w[t] ? slot_of[T.blk[t]] : 0u;
 #pragma unroll
-            for (int k = 0; k < kLevels; k++) {
-                uint32_t acc[3] = {0, 0, 0};
-#pragma unroll
-                for (int j = 0; j < kPer; j++) {
-                    const int t = k * kPer + j;
-                    const uint32_t w = T.w[t];
-                    missing |= (w != 0) && slot[t] == JPT_SLOT_NONE;
-                    const uint32_t v = tex[t];
-                    acc[0] += (v & 255) * w;
-                    acc[1] += ((v >> 8) & 255) * w;
-                    acc[2] += ((v >> 16) & 255) * w;
-                }
-#pragma unroll
-                for (int c = 0; c < 3; c++) lvl[k][c] = (acc[c] + 32768u) >> 16;
-            }
-            if (missing) {
+            for (int t = 0; t < kTaps; t++)
+                tex[t] = (T.w[t] && slot[t] != JPT_SLOT_NONE) ? texels[(size_t)slot[t] * 256 + T.off[t]] : 0u;
+            if (x >= W || y >= H) continue;
+            uint32_t out;
+            if (st == PIX_BACKGROUND) {
+                out = 0;
+            } else if (st == PIX_INVALID) {
                 out = JPT_TEXEL_INVALID;
             } else {
-                uint32_t a[3] = {lvl[0][0], lvl[0][1], lvl[0][2]};
-                if (kFilter == JPT_FILTER_TRILINEAR && nf == 2) {
+                bool missing = false;
+                uint32_t lvl[2][3] = {{0, 0, 0}, {0, 0, 0}};
+                constexpr int kLevels = kTaps == 8 ? 2 : 1, kPer = kTaps == 1 ? 1 : 4;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) a[c] = (lvl[0][c] * (256 - tw) + lvl[1][c] * tw + 128) >> 8;
+                for (int k = 0; k < kLevels; k++) {
+                    uint32_t acc[3] = {0, 0, 0};
+#pragma unroll
+                    for (int j = 0; j < kPer; j++) {
+                        const int t = k * kPer + j;
+                        const uint32_t w = T.w[t];
+                        missing |= (w != 0) && slot[t] == JPT_SLOT_NONE;
+                        const uint32_t v = tex[t];
+                        acc[0] += (v & 255) * w;
+                        acc[1] += ((v >> 8) & 255) * w;
+                        acc[2] += ((v >> 16) & 255) * w;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; c++) lvl[k][c] = (acc[c] + 32768u) >> 16;
                 }
-                out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
+                if (missing) {
+                    out = JPT_TEXEL_INVALID;
+                } else {
+                    uint32_t a[3] = {lvl[0][0], lvl[0][1], lvl[0][2]};
+                    if (kFilter == JPT_FILTER_TRILINEAR && nf == 2) {
+#pragma unroll
+                        for (int c = 0; c < 3; c++) a[c] = (lvl[0][c] * (256 - tw) + lvl[1][c] * tw + 128) >> 8;
+                    }
+                    out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
+                }
             }
+            frame[(size_t)y * frame_pitch + x] = out;
         }
-        frame[(size_t)y * frame_pitch + x] = out;
     }
 }
 
 template <uint32_t kFilter>
-void launch(const jpt_scene *scene, const jpt_view &V, const jpt_cache *cache, hipStream_t st) {
-    dim3 grid((V.width + kTileW - 1) / kTileW, (V.height + kTileH - 1) / kTileH);
+void launch(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache, hipStream_t st) {
     if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
-        hipLaunchKernelGGL((k_resolve<kFilter, true>), grid, dim3(kThreads), 0, st, scene->levels, scene->textures,
-                           scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, cache->slot_of,
-                           cache->texels, V.frame, V.frame_pitch);
+        hipLaunchKernelGGL((k_resolve<kFilter, true>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
     else
-        hipLaunchKernelGGL((k_resolve<kFilter, false>), grid, dim3(kThreads), 0, st, scene->levels, scene->textures,
-                           scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, cache->slot_of,
-                           cache->texels, V.frame, V.frame_pitch);
+        hipLaunchKernelGGL((k_resolve<kFilter, false>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
 }
 
 }  // namespace
@@ -161,7 +165,6 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
                                   const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning,
                                   void *stream) {
     (void)frame;
-    (void)tuning;
     if (!scene || (n_views && !views) || !cache || !cache->slot_of || !cache->texels) return JPT_E_ARG;
     if (filter > JPT_FILTER_TRILINEAR || !scene->levels || !scene->textures) return JPT_E_ARG;
     for (uint32_t v = 0; v < n_views; v++)
@@ -169,12 +172,18 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
             views[v].frame_pitch < views[v].width)
             return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
-    for (uint32_t v = 0; v < n_views; v++) {
-        const jpt_view &V = views[v];
-        if (V.width == 0 || V.height == 0) continue;
-        if (filter == JPT_FILTER_NEAREST) launch<JPT_FILTER_NEAREST>(scene, V, cache, st);
-        else if (filter == JPT_FILTER_BILINEAR) launch<JPT_FILTER_BILINEAR>(scene, V, cache, st);
-        else launch<JPT_FILTER_TRILINEAR>(scene, V, cache, st);
+    const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
+    for (uint32_t v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
+        ViewTable tab;
+        make_view_table(views, v0, n_views - v0 < kMaxLaunchViews ? n_views - v0 : kMaxLaunchViews, kTileW, kTileH,
+                        xcd, tab);
+        if (tab.total == 0) continue;
+        uint32_t groups = tab.span;
+        if (tuning && tuning->resolve_groups && tuning->resolve_groups < groups)
+            groups = xcd ? (tuning->resolve_groups + 7) / 8 * 8 : tuning->resolve_groups;
+        if (filter == JPT_FILTER_NEAREST) launch<JPT_FILTER_NEAREST>(scene, tab, groups, cache, st);
+        else if (filter == JPT_FILTER_BILINEAR) launch<JPT_FILTER_BILINEAR>(scene, tab, groups, cache, st);
+        else launch<JPT_FILTER_TRILINEAR>(scene, tab, groups, cache, st);
         HIP_CHECK_LAUNCH();
     }
     return JPT_OK;

@@ -25,6 +25,8 @@ JPT_OK, JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT, JPT_E_RANGE, JPT_E_BUFSIZE,
 FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR = 0, 1, 2
 CACHE_NONE, CACHE_LRU = 0, 1
 IDCT_MFMA_F16, IDCT_SCALAR_F32 = 0, 1
+FRAME_AUTO = 0xFFFFFFFF
+TUNE_XCD_TILES = 1
 CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT = range(7)
 N_COUNTERS = 16
 ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL = 1, 2, 4
@@ -82,7 +84,8 @@ CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1
 
 
 class TuningC(ctypes.Structure):
-    _fields_ = [("decode_groups", u32), ("idct_groups", u32), ("reserved", u32 * 6)]
+    _fields_ = [("decode_groups", u32), ("idct_groups", u32), ("mark_groups", u32), ("resolve_groups", u32),
+                ("flags", u32), ("reserved", u32 * 3)]
 
 
 assert ctypes.sizeof(LevelDesc) == 64 and ctypes.sizeof(TextureDesc) == 16
@@ -101,9 +104,12 @@ SIGNATURES = {
     "jpt_idct_color": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_resolve": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
     "jpt_cache_reset": (ctypes.c_int32, [vp, vp, vp]),
-    "jpt_dequantize": (ctypes.c_int32, [vp, vp, vp, vp]),
-    "jpt_fwd_float": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp]),
-    "jpt_backward": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp]),
+    "jpt_graph_capture": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, u32, vp, vp, ctypes.POINTER(vp)]),
+    "jpt_graph_launch": (ctypes.c_int32, [vp, vp]),
+    "jpt_graph_destroy": (ctypes.c_int32, [vp]),
+    "jpt_dequantize": (ctypes.c_int32, [vp, vp, vp, u32, vp]),
+    "jpt_fwd_float": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, u32, vp, vp, vp]),
+    "jpt_backward": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, u32, vp]),
     "jpt_version": (u32, []),
     "jpt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
 }
@@ -416,10 +422,12 @@ def resolve(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Ca
 
 
 class Renderer:
-    """One frame of the plain form: mark -> decode -> resolve on the current stream."""
+    """One frame of the plain form: mark -> decode -> resolve on the current
+    stream, over one or more views.  `tuning` (TuningC or None) holds launch
+    knobs; `frame_no = FRAME_AUTO` lets an LRU cache count frames itself."""
 
     def __init__(self, textures, gbufs, filt, device="cuda", max_items=None, n_slots=None, host=None,
-                 policy=CACHE_NONE):
+                 policy=CACHE_NONE, tuning=None, idct_mode=IDCT_MFMA_F16):
         self.host = host or HostScene(textures)
         self.scene = DeviceScene(self.host, device)
         self.views = Views(gbufs, device)
@@ -430,6 +438,8 @@ class Renderer:
         self.frame = Frame(self.scene, self.max_items)
         self.cache = Cache(self.scene, int(n_slots or min(self.host.n_blocks, self.max_items)), policy)
         self.frame_no = 0
+        self.tuning = tuning
+        self.idct_mode = idct_mode
 
     def set_views(self, gbufs):
         """Load new G-buffers (same sizes) into the existing view buffers."""
@@ -440,19 +450,57 @@ class Renderer:
 
     def mark(self, stream=None):
         self.frame.c.frame_no = self.frame_no
-        mark_blocks(self.scene, self.views, self.filter, self.frame, self.cache, stream=stream)
-        self.frame_no += 1
+        mark_blocks(self.scene, self.views, self.filter, self.frame, self.cache, self.tuning, stream=stream)
+        if self.frame_no != FRAME_AUTO:
+            self.frame_no += 1
 
-    def decode(self, stream=None, idct_mode=IDCT_MFMA_F16):
-        decode_blocks(self.scene, self.frame, self.cache, idct_mode, stream=stream)
+    def decode(self, stream=None, idct_mode=None):
+        decode_blocks(self.scene, self.frame, self.cache, self.idct_mode if idct_mode is None else idct_mode,
+                      self.tuning, stream=stream)
 
     def resolve(self, stream=None):
-        resolve(self.scene, self.views, self.filter, self.frame, self.cache, stream=stream)
+        resolve(self.scene, self.views, self.filter, self.frame, self.cache, self.tuning, stream=stream)
 
     def render(self, stream=None):
         self.mark(stream)
         self.decode(stream)
         self.resolve(stream)
+
+    def capture(self, stream):
+        """The batched form: capture one frame of every view into a HIP graph
+        (jpt_graph_capture) on `stream`, a torch.cuda.Stream other than the
+        default one.  With an LRU cache the renderer switches to FRAME_AUTO."""
+        if self.cache.policy == CACHE_LRU:
+            self.frame_no = FRAME_AUTO
+        self.frame.c.frame_no = self.frame_no
+        return Graph(self, stream)
+
+
+class Graph:
+    """A captured frame (jpt_graph); launch() replays it on its stream."""
+
+    def __init__(self, r: Renderer, stream):
+        self.r = r
+        self.stream = stream
+        h = vp()
+        _check("jpt_graph_capture", lib().jpt_graph_capture(
+            ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
+            r.idct_mode, ctypes.byref(r.tuning) if r.tuning else None, vp(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self):
+        _check("jpt_graph_launch", lib().jpt_graph_launch(self.h, vp(self.stream.cuda_stream)))
+
+    def close(self):
+        if self.h:
+            lib().jpt_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class DiffFrame:
@@ -484,7 +532,7 @@ class DiffFrame:
         F = torch.empty((self.n_items(), ITEMS_DU, 64), dtype=torch.float32, device=self.r.scene.device)
         if F.numel():
             _check("jpt_dequantize", lib().jpt_dequantize(ctypes.byref(self.r.scene.c), ctypes.byref(self.r.frame.c),
-                                                          vp(F.data_ptr()), stream or current_stream()))
+                                                          vp(F.data_ptr()), F.shape[0], stream or current_stream()))
         return F
 
     def forward(self, F, stream=None):
@@ -495,7 +543,8 @@ class DiffFrame:
         r = self.r
         _check("jpt_fwd_float", lib().jpt_fwd_float(
             ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
-            vp(F.data_ptr()), vp(self.texel_f.data_ptr()), vp(frame_f.data_ptr()), stream or current_stream()))
+            vp(F.data_ptr()), F.shape[0], vp(self.texel_f.data_ptr()), vp(frame_f.data_ptr()),
+            stream or current_stream()))
         return frame_f
 
     def backward(self, dframe, F_shape, stream=None):
@@ -507,7 +556,8 @@ class DiffFrame:
         r = self.r
         _check("jpt_backward", lib().jpt_backward(
             ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
-            vp(dframe.data_ptr()), vp(self.dtexel.data_ptr()), vp(dF.data_ptr()), stream or current_stream()))
+            vp(dframe.data_ptr()), vp(self.dtexel.data_ptr()), vp(dF.data_ptr()), F_shape[0],
+            stream or current_stream()))
         return dF
 
     def _check_F(self, F):

@@ -116,3 +116,61 @@ def heavy(seed=3, n_tex=256, sides=(512, 1024, 2048, 4096, 8192), q_lo=40, q_hi=
     return Workload(name or "heavy %d tex, %dx%d, %d frames" % (n_tex, W, H, n_frames), textures, frames,
                     FILTER_TRILINEAR, dict(quads=quads, qualities=qs.tolist(), sides=side.tolist(),
                                            sampling=smp.tolist()))
+
+
+def batched(seed=4, n_pool=128, sides=(512, 1024, 2048, 4096), q_lo=50, q_hi=90, n_pairs=2,
+            eye=(2064, 2208), n_mono=12, mono_w=(1280, 2560), tex_per_scene=(8, 64), quads_per_mpx=96,
+            filt=FILTER_BILINEAR, name=None) -> Workload:
+    """Batched recipe: a pool of n_pool 4:2:0 textures (side uniform over
+    `sides`, q ~ U{q_lo..q_hi}, full mip chains) seen by n_pairs stereo
+    pairs of eye[0] x eye[1] pixels per eye and n_mono mono views of width
+    ~ U[mono_w] at 16:9.  Each scene (a stereo pair shares one) draws its
+    own subset of tex_per_scene textures and quads_per_mpx quads per
+    megapixel; the second eye sees the first eye's quads shifted by a
+    horizontal disparity of 3% of its width.  Views: pairs first, then mono."""
+    ss = np.random.SeedSequence(seed)
+    tex_seq, prm_seq, scene_seq = ss.spawn(3)
+    tex_seeds = [int(s.generate_state(1, np.uint64)[0]) for s in tex_seq.spawn(n_pool)]
+    prm = np.random.default_rng(prm_seq)
+    side = prm.choice(np.array(sides), n_pool)
+    qs = prm.integers(q_lo, q_hi + 1, n_pool)
+    specs = [(tex_seeds[i], int(side[i]), int(side[i]), int(qs[i]), 420, None) for i in range(n_pool)]
+    textures = make_textures(specs)
+    sizes = {i: (float(side[i]), float(side[i])) for i in range(n_pool)}
+    rng = np.random.default_rng(scene_seq)
+    from . import similarity
+    views, shapes = [], []
+
+    def scene(W, H):
+        k = int(rng.integers(tex_per_scene[0], tex_per_scene[1] + 1))
+        ids = sorted(rng.choice(n_pool, min(k, n_pool), replace=False).tolist())
+        nq = max(1, int(round(quads_per_mpx * W * H / 1e6)))
+        return random_quads(rng, W, H, nq, ids, sizes)
+
+    for _ in range(n_pairs):
+        W, H = eye
+        quads = scene(W, H)
+        views.append(rasterise(W, H, quads))
+        views.append(rasterise(W, H, quads, similarity(-0.03 * W, 0.0, 0.0, 1.0, W, H)))
+        shapes += [(W, H)] * 2
+    for _ in range(n_mono):
+        W = int(rng.integers(mono_w[0] // 16, mono_w[1] // 16 + 1)) * 16
+        H = W * 9 // 16
+        views.append(rasterise(W, H, scene(W, H)))
+        shapes.append((W, H))
+    return Workload(name or "batched %d views (%d stereo pairs %dx%d + %d mono), %d-texture pool"
+                    % (len(views), n_pairs, eye[0], eye[1], n_mono, n_pool), textures, views, filt,
+                    dict(shapes=shapes, sides=side.tolist(), qualities=qs.tolist()))
+
+
+def batched16() -> Workload:
+    """The 16-view batch: 2 stereo pairs of 2064x2208 + 12 mono views from
+    1280x720 to 2560x1440 over a 128-texture pool of sides 512..4096."""
+    return batched()
+
+
+def batched_small(seed=6, filt=FILTER_BILINEAR) -> Workload:
+    """The batched recipe at a size the CPU checker finishes quickly."""
+    return batched(seed=seed, n_pool=10, sides=(64, 128, 256), n_pairs=1, eye=(96, 104), n_mono=3,
+                   mono_w=(64, 160), tex_per_scene=(2, 6), quads_per_mpx=2000, filt=filt,
+                   name="batched small")

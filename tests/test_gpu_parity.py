@@ -12,49 +12,9 @@ import oracle
 from oracle import parity
 from paper_2510_08166_amd.synth import configs
 
+from gpu_common import full_parity, run
+
 pytestmark = pytest.mark.gpu
-
-
-def run(wl, **kw):
-    import torch
-    from paper_2510_08166_amd import jpt
-    r = jpt.Renderer(wl.textures, wl.views, wl.filter, **kw)
-    r.render()
-    torch.cuda.synchronize()
-    ctr = r.frame.counters_host()
-    items = r.frame.work_items()
-    n = len(items)
-    coef = r.frame.coef[: n * jpt.ITEM_COEFS].cpu().numpy().reshape(n, 6, 64)
-    n_new = min(int(ctr[jpt.CTR_NEW]), r.cache.n_slots)
-    tiles = r.cache.texels[: n_new * 256].cpu().numpy().view(np.uint32).reshape(n_new, 256)
-    frames = [r.views.frame_host(i) for i in range(r.views.n)]
-    return r, ctr, items, coef, tiles, frames
-
-
-def full_parity(wl, coef_sample=None, texel_sample=None, full_render=True):
-    from paper_2510_08166_amd import jpt
-    osc = oracle.Scene(wl.textures)
-    r, ctr, items, coef, tiles, frames = run(wl)
-    print("%s: items %d new %d visible %d err %x" % (wl.name, ctr[jpt.CTR_ITEMS], ctr[jpt.CTR_NEW],
-                                                     ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_ERROR]), flush=True)
-    assert ctr[jpt.CTR_ERROR] == 0
-    blocks = parity.visible_blocks(osc, wl.views, wl.filter)
-    assert ctr[jpt.CTR_NEW] == len(blocks) and ctr[jpt.CTR_VISIBLE] == len(blocks)
-    assert np.array_equal(items, parity.expected_items(osc, blocks))
-    lc = parity.LevelCache(osc)
-    assert parity.check_coefs(lc, items, coef, coef_sample) == []
-    maxd, nmis, tie, n = parity.check_texels(lc, blocks, tiles, texel_sample)
-    print("texels: max diff %d, %d of %d channels differ, worst tie distance %.2e" % (maxd, nmis, n, tie))
-    assert maxd <= 1 and tie < 0.01
-    imgs = parity.levels_from_tiles(osc, blocks, tiles)
-    for g, f in zip(wl.views, frames):
-        ref, bad = osc.resolve(g, wl.filter, imgs)
-        assert bad == 0
-        assert np.array_equal(f, ref), "frame differs from the oracle's resolve of the GPU texels"
-        if full_render:
-            full, _, _ = osc.render(g, wl.filter)
-            assert parity.frame_diff(f, full) <= 1
-    return r, osc, blocks
 
 
 def test_tiny_all_blocks(gpu):
@@ -79,6 +39,17 @@ def test_reduced_444_and_ragged(gpu):
     wl = configs.quad_scene(21, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444,
                             filt=configs.FILTER_BILINEAR, name="444 ragged")
     full_parity(wl)
+
+
+@pytest.mark.parametrize("case", ["420 trilinear", "444 ragged"])
+def test_scalar_f32_idct(gpu, case):
+    """The separable fp32 IDCT (JPT_IDCT_SCALAR_F32) to the same bar as the MFMA one."""
+    from paper_2510_08166_amd import jpt
+    if case == "444 ragged":
+        wl = configs.quad_scene(22, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444, filt=configs.FILTER_BILINEAR)
+    else:
+        wl = configs.reduced(seed=12, filt=configs.FILTER_TRILINEAR)
+    full_parity(wl, idct_mode=jpt.IDCT_SCALAR_F32)
 
 
 def test_many_tiles(gpu):
