@@ -265,6 +265,109 @@ def diff_form(args):
             "fwd_ms_median": round(float(np.median(fw)), 4), "bwd_ms_median": round(float(np.median(bw)), 4)}
 
 
+def heavy_form(args, reps=None):
+    """Heavy recipe: 256 textures (512..8192, q40-95, 4:2:0 / 4:4:4, full
+    chains), 3840x2160, trilinear, an LRU cache of 2 GiB of texel slots, 8
+    frames of camera drift.  One frame = one graph launch (the cache counts
+    frames on the device); the 8-frame sequence runs `reps` times from an
+    empty cache.  Reports the mean over frames of the per-frame median and
+    the max of the per-frame medians."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    from paper_2510_08166_amd.synth import configs
+    t0 = time.perf_counter()
+    wl = configs.heavy()
+    log("heavy workload generated in %.1f s" % (time.perf_counter() - t0))
+    slots = (2 << 30) // 1024
+    t0 = time.perf_counter()
+    r = jpt.Renderer(wl.textures, [wl.views[0]], wl.filter, device="cuda:0", policy=jpt.CACHE_LRU, n_slots=slots,
+                     max_items=1 << 20)
+    views = [jpt.Views([g]) for g in wl.views]
+    torch.cuda.synchronize()
+    log("index built and uploaded in %.1f s (%d block ids, %.2f GB compressed)" % (
+        time.perf_counter() - t0, r.scene.n_blocks, r.scene.compressed_bytes() / 1e9))
+    # eager pass, frame by frame: error flags and per-frame counts
+    counts = []
+    r.frame_no = jpt.FRAME_AUTO
+    for v in views:
+        r.views = v
+        r.render()
+        torch.cuda.synchronize()
+        c = r.frame.counters_host()
+        if c[jpt.CTR_ERROR]:
+            raise SystemExit("device error flags %x" % c[jpt.CTR_ERROR])
+        counts.append((int(c[jpt.CTR_VISIBLE]), int(c[jpt.CTR_NEW]), int(c[jpt.CTR_EVICTED])))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graphs = [r.capture(side, v) for v in views]
+    reps = reps or max(3, args.steps // len(views))
+    nf = len(views)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(nf + 1)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for rep in range(reps):
+        r.cache.reset(r.scene, jpt.vp(side.cuda_stream))
+        ev[rep][0].record(side)
+        for f in range(nf):
+            graphs[f].launch()
+            ev[rep][f + 1].record(side)
+    side.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([[ev[k][f].elapsed_time(ev[k][f + 1]) for f in range(nf)] for k in range(reps)])
+    med = np.median(per, axis=0)
+    for g in graphs:
+        g.close()
+    c = r.frame.counters_host()
+    if c[jpt.CTR_ERROR]:
+        raise SystemExit("device error flags %x after the timed sequences" % c[jpt.CTR_ERROR])
+    return {"metric": METRIC, "value": round(float(med.mean()), 4), "unit": "ms/frame", "n_gpus": 1,
+            "steps": reps * nf, "warmup": 0, "ms_per_step": round(1000.0 * wall / (reps * nf), 4),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic",
+            "config": {"workload": wl.name + ", trilinear, LRU 2 GiB", "frames": nf, "repetitions": reps,
+                       "pixels_per_frame": int(wl.views[0].size), "block_ids": int(r.scene.n_blocks)},
+            "per_frame_ms_median": [round(float(x), 4) for x in med],
+            "max_of_medians_ms": round(float(med.max()), 4),
+            "frames_visible_new_evicted": counts}
+
+
+def batched_extras(args, r, out):
+    """Batched form: tune the launch knobs (results must not change), time
+    the tuned graph, and compare the MFMA fp16 IDCT with the fp32 scalar one
+    (time of the IDCT phase, texel differences between the two)."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt, tune
+    t0 = time.perf_counter()
+    knobs = tune.tune(r, reps=5, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"), log=log)
+    log("tuned in %.1f s: %s" % (time.perf_counter() - t0, tune.to_dict(knobs)))
+    ms_tuned, gpu_tuned = time_graph(r, args.steps, args.warmup)
+    ex = {"tuning": tune.to_dict(knobs), "value_default_knobs": out["value"],
+          "gpu_ms_per_frame_median_tuned": round(float(np.median(gpu_tuned)), 4)}
+    out["value"] = out["ms_per_step"] = round(ms_tuned, 4)
+    # IDCT modes
+    r.render()
+    torch.cuda.synchronize()
+    n_new = min(int(r.frame.counters_host()[jpt.CTR_NEW]), r.cache.n_slots)
+    tex_mfma = r.cache.texels[: n_new * 256].clone()
+    times = {}
+    for mode, name in ((jpt.IDCT_MFMA_F16, "mfma_f16"), (jpt.IDCT_SCALAR_F32, "scalar_f32")):
+        r.idct_mode = mode
+        _, med = time_phases(r, args.steps)
+        times[name] = round(float(med[2]), 4)
+    torch.cuda.synchronize()
+    tex_sc = r.cache.texels[: n_new * 256]
+    a = tex_mfma.cpu().numpy().view(np.uint8).astype(np.int16)
+    b = tex_sc.cpu().numpy().view(np.uint8).astype(np.int16)
+    d = np.abs(a - b)
+    r.idct_mode = jpt.IDCT_MFMA_F16
+    ex["idct_ms"] = times
+    ex["idct_mfma_vs_scalar"] = {"max_abs_diff": int(d.max()), "channels_differing": int((d > 0).sum()),
+                                 "channels": int(d.size)}
+    return ex
+
+
 def calibrate_copy():
     """One device copy of 1 GiB, for scaling the FETCH_SIZE / WRITE_SIZE
     counters of a profiled run to bytes."""
@@ -283,7 +386,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="frame1080", choices=["frame1080", "batched16", "diff1080"])
+    ap.add_argument("--workload", default="frame1080", choices=["frame1080", "batched16", "diff1080", "heavy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -300,6 +403,9 @@ def main():
     if args.workload == "diff1080":
         print(json.dumps(diff_form(args)), flush=True)
         return
+    if args.workload == "heavy":
+        print(json.dumps(heavy_form(args)), flush=True)
+        return
     t0 = time.perf_counter()
     if args.workload == "frame1080":
         wl = configs.frame1080()
@@ -311,6 +417,8 @@ def main():
                  "pool (512..4096, q50-90, 4:2:0), one graph launch per frame, bilinear, no cache")
     log("workload generated in %.1f s" % (time.perf_counter() - t0))
     r, out = plain_form(args, wl, label)
+    if args.workload == "batched16":
+        out.update(batched_extras(args, r, out))
     if args.workload == "frame1080" and not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

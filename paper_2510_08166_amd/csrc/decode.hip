@@ -118,16 +118,21 @@ __global__ __launch_bounds__(64) void k_entropy(const jpt_level_desc *__restrict
                 mcu = by * mcu_cols + bx;
             }
             if (active) {
+                // the five record words this MCU needs, loaded together from
+                // in-bounds addresses (word 16 is the next record's anchor, read
+                // only when that record exists)
                 const uint32_t g = mcu / 9, j = mcu - g * 9;
                 const gu32 rec = recs + (size_t)g * 16;
-                const uint32_t anchor = rec[0];
-                const uint32_t rel = j ? (rec[1 + ((j - 1) >> 1)] >> (((j - 1) & 1) * 16)) & 0xFFFFu : 0u;
-                start = anchor + rel;
-                end = (mcu + 1 >= n_mcu) ? stream_bits
-                                         : (j < 8 ? anchor + ((rec[1 + (j >> 1)] >> ((j & 1) * 16)) & 0xFFFFu)
-                                                  : rec[16]);
+                const bool last = mcu + 1 >= n_mcu;
+                const uint32_t i1 = j ? 1 + ((j - 1) >> 1) : 0u;
+                const uint32_t i2 = last ? 0u : (j < 8 ? 1 + (j >> 1) : 16u);
                 const uint32_t bp = 160 + 36 * j;
-                const uint64_t dv = ((((uint64_t)rec[(bp >> 5) + 1]) << 32) | rec[bp >> 5]) >> (bp & 31);
+                const uint32_t anchor = rec[0], w1 = rec[i1], w2 = rec[i2];
+                const uint32_t d0 = rec[bp >> 5], d1 = rec[(bp >> 5) + 1];
+                const uint32_t rel = j ? (w1 >> (((j - 1) & 1) * 16)) & 0xFFFFu : 0u;
+                start = anchor + rel;
+                end = last ? stream_bits : (j < 8 ? anchor + ((w2 >> ((j & 1) * 16)) & 0xFFFFu) : w2);
+                const uint64_t dv = ((((uint64_t)d1) << 32) | d0) >> (bp & 31);
                 dc0 = sext12((uint32_t)dv & 0xFFFu);
                 dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu);
                 dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
@@ -139,19 +144,24 @@ __global__ __launch_bounds__(64) void k_entropy(const jpt_level_desc *__restrict
         {
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
             typedef const __attribute__((address_space(1))) u32x4 *gu32x4;
+            // unconditional loads from clamped in-bounds addresses (the stream
+            // holds at least 4 words), zeroed afterwards, so that no branch
+            // forces a wait between them
             u32x4 v[kWin / 4];
+            const uint32_t last = limit >= 4u ? limit - 4u : 0u;
+            const gu32 src = active ? stream : (gu32)tables;  // any valid 16-byte aligned address
 #pragma unroll
             for (int i = 0; i < kWin / 4; i++) {
                 const uint32_t wi = wbase + 4 * i;
-                v[i] = u32x4{0u, 0u, 0u, 0u};
-                if (active && wi < limit) v[i] = *(gu32x4)(stream + wi);
+                v[i] = *(gu32x4)(src + (active ? min(wi, last) : 0u));
             }
 #pragma unroll
             for (int i = 0; i < kWin / 4; i++) {
-                s_win[(4 * i + 0) * 64 + lane] = v[i].x;
-                s_win[(4 * i + 1) * 64 + lane] = v[i].y;
-                s_win[(4 * i + 2) * 64 + lane] = v[i].z;
-                s_win[(4 * i + 3) * 64 + lane] = v[i].w;
+                const bool ok = active && wbase + 4 * i < limit;
+                s_win[(4 * i + 0) * 64 + lane] = ok ? v[i].x : 0u;
+                s_win[(4 * i + 1) * 64 + lane] = ok ? v[i].y : 0u;
+                s_win[(4 * i + 2) * 64 + lane] = ok ? v[i].z : 0u;
+                s_win[(4 * i + 3) * 64 + lane] = ok ? v[i].w : 0u;
             }
         }
         __syncthreads();
@@ -292,13 +302,14 @@ __device__ __forceinline__ uint32_t ycc_to_rgba(float Y, float Cb, float Cr) {
     return R | (G << 8) | (B << 16) | 0xFF000000u;
 }
 
-constexpr int kIdctItems = 16;                       // items per wave iteration
+constexpr int kIdctItems = 16;                       // items per workgroup iteration
 constexpr int kIdctUnits = kIdctItems * JPT_ITEMS_DU;  // 96 = 3 column tiles of 32
+constexpr int kIdctThreads = 256;                      // waves 0-2: one column tile each; all 4: colour
 
 // per-item flags gathered once per tile
 constexpr uint32_t kItem444 = 1u, kItemFailed = 2u, kItemPresent = 4u, kItemValid = 8u;
 
-__global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restrict__ levels,
+__global__ __launch_bounds__(kIdctThreads) void k_idct_mfma(const jpt_level_desc *__restrict__ levels,
                                                   const uint32_t *__restrict__ word_level,
                                                   const uint16_t *__restrict__ quant, const uint32_t *__restrict__ work,
                                                   const uint32_t *__restrict__ counters,
@@ -308,33 +319,35 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
     __shared__ float s_samp[kIdctUnits * 64];
     __shared__ float s_P[64];
     __shared__ uint32_t s_slot[kIdctItems], s_quant[kIdctItems], s_flags[kIdctItems], s_q[kIdctItems];
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t n_items = counters[JPT_CTR_ITEMS];
     if (blockIdx.x * (uint32_t)kIdctItems >= n_items) return;
     const uint32_t col = lane & 31, half = lane >> 5;
 
     // basis operands: A[m][s] holds K[32m + col][16s + 8 half + t], t = 0..7, built
     // from the 1-D table P[u][x] = C(u)/2 cos((2x+1) u pi / 16)
-    s_P[lane] = basis1d((int)(lane >> 3), (int)(lane & 7));
+    if (threadIdx.x < 64) s_P[lane] = basis1d((int)(lane >> 3), (int)(lane & 7));
     __syncthreads();
     half8 Khi[2][4], Klo[2][4];
+    if (wv < kIdctUnits / 32) {
 #pragma unroll
-    for (int m = 0; m < 2; m++)
+        for (int m = 0; m < 2; m++)
 #pragma unroll
-        for (int s = 0; s < 4; s++)
+            for (int s = 0; s < 4; s++)
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const int i = 32 * m + (int)col;                     // pixel y*8+x
-                const int n = kZigZag.nat[16 * s + 8 * half + t];     // natural v*8+u
-                const float K = s_P[(n & 7) * 8 + (i & 7)] * s_P[(n >> 3) * 8 + (i >> 3)];
-                const _Float16 hi = (_Float16)K;
-                Khi[m][s][t] = hi;
-                Klo[m][s][t] = (_Float16)((K - (float)hi) * 2048.0f);
-            }
+                for (int t = 0; t < 8; t++) {
+                    const int i = 32 * m + (int)col;                     // pixel y*8+x
+                    const int n = kZigZag.nat[16 * s + 8 * half + t];     // natural v*8+u
+                    const float K = s_P[(n & 7) * 8 + (i & 7)] * s_P[(n >> 3) * 8 + (i >> 3)];
+                    const _Float16 hi = (_Float16)K;
+                    Khi[m][s][t] = hi;
+                    Klo[m][s][t] = (_Float16)((K - (float)hi) * 2048.0f);
+                }
+    }
 
     for (uint32_t base = blockIdx.x * kIdctItems; base < n_items; base += gridDim.x * kIdctItems) {
-        // ---- item metadata, one lane per item
-        if (lane < (uint32_t)kIdctItems) {
+        // ---- item metadata, one lane of the last wave per item
+        if (wv == kIdctThreads / 64 - 1 && lane < (uint32_t)kIdctItems) {
             const uint32_t it = base + lane;
             uint32_t flags = 0, slot = JPT_SLOT_NONE, qi = 0, q = 0;
             if (it < n_items) {
@@ -357,9 +370,8 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
             s_slot[lane] = slot; s_quant[lane] = qi; s_flags[lane] = flags; s_q[lane] = q;
         }
         __syncthreads();
-#pragma unroll
-        for (int ct = 0; ct < kIdctUnits / 32; ct++) {
-            const uint32_t d = 32 * ct + col;
+        if (wv < kIdctUnits / 32) {
+            const uint32_t d = 32 * wv + col;
             const uint32_t li = d / JPT_ITEMS_DU, du = d % JPT_ITEMS_DU;
             const uint32_t flags = s_flags[li];
             int fv[4][8];
@@ -433,8 +445,8 @@ __global__ __launch_bounds__(64) void k_idct_mfma(const jpt_level_desc *__restri
             }
         }
         __syncthreads();
-        // colour conversion and store, one item at a time (1 KiB per 4:2:0 item)
-        for (int li = 0; li < kIdctItems; li++) {
+        // colour conversion and store, wave w takes items w, w+4, ... (1 KiB per 4:2:0 item)
+        for (int li = (int)wv; li < kIdctItems; li += kIdctThreads / 64) {
             const uint32_t flags = s_flags[li], slot = s_slot[li];
             if (!(flags & kItemValid)) break;
             if (slot == JPT_SLOT_NONE || !(flags & kItemPresent)) continue;
@@ -606,7 +618,8 @@ extern "C" jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, j
     if (s) return s;
     if (!cache || !cache->texels || !cache->slot_of) return JPT_E_ARG;
     if (idct_mode == JPT_IDCT_MFMA_F16)
-        hipLaunchKernelGGL(k_idct_mfma, dim3(default_groups(tuning, true)), dim3(64), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(k_idct_mfma, dim3(default_groups(tuning, true)), dim3(kIdctThreads), 0,
+                           (hipStream_t)stream,
                            scene->levels, scene->word_level, scene->quant, frame->work, frame->counters, frame->coef,
                            cache->slot_of, cache->texels);
     else if (idct_mode == JPT_IDCT_SCALAR_F32)

@@ -44,13 +44,19 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
 }
 
 // One workgroup marks one 64 x 32 pixel tile per step and walks the tiles of
-// every view in the launch's table with a stride of gridDim.x.
-template <bool kLdsDesc>
+// every view in the launch's table with a stride of gridDim.x.  A wave takes
+// rows wv, wv+4, ... of the tile, one row per step with the next row's
+// G-buffer load in flight.  Each lane drops the block ids that its left
+// neighbour (the previous pixel of the row) also touches, and inserts the
+// rest into the tile's LDS set; the set is flushed to the bitmask with one
+// HBM atomic per distinct word.
+template <uint32_t kFilter, bool kLdsDesc>
 __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
-                                                       uint32_t n_lev, const ViewTable tab, uint32_t filter,
+                                                       uint32_t n_lev, const ViewTable tab,
                                                        uint32_t *__restrict__ vis, uint32_t *__restrict__ counters) {
     constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
+    constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize];
     __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
@@ -64,39 +70,39 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
         if (!tile_of(tab, slot, view, tx, ty)) continue;  // uniform over the workgroup
         const jpt_gpixel *__restrict__ gbuf = tab.v[view].gbuf;
         const uint32_t W = tab.v[view].width, H = tab.v[view].height, pitch = tab.v[view].pitch;
-        const uint32_t x = tx * kTileW + lane;
-        // all of this lane's G-buffer pixels in flight at once (rows wv, wv+4, ...)
-        jpt_gpixel px[kRows];
-#pragma unroll
-        for (int r = 0; r < kRows; r++) {
-            const uint32_t y = ty * kTileH + wv + r * (kMarkThreads / 64);
-            px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
-        }
+        const uint32_t x = tx * kTileW + lane, y0 = ty * kTileH + wv;
+        jpt_gpixel nxt = (x < W && y0 < H) ? gbuf[(size_t)y0 * pitch + x]
+                                           : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
         for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
             s_key[i] = 0xFFFFFFFFu;
             s_bits[i] = 0;
         }
         __syncthreads();
-#pragma unroll
+#pragma unroll 1
         for (int r = 0; r < kRows; r++) {
-            uint32_t ids[8];
+            const jpt_gpixel px = nxt;
+            const uint32_t yn = y0 + (r + 1) * (kMarkThreads / 64);
+            if (r + 1 < kRows)
+                nxt = (x < W && yn < H) ? gbuf[(size_t)yn * pitch + x]
+                                        : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+            uint32_t ids[kIds];
 #pragma unroll
-            for (int k = 0; k < 8; k++) ids[k] = 0xFFFFFFFFu;
+            for (int k = 0; k < kIds; k++) ids[k] = 0xFFFFFFFFu;
             LevelFoot foot[2];
             int nf;
             uint32_t tw;
             int st;
-            if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px[r], filter, foot, nf, tw);
-            else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px[r], filter, foot, nf, tw);
+            if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px, kFilter, foot, nf, tw);
+            else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw);
             if (st == PIX_INVALID) {
                 invalid = true;
             } else if (st == PIX_VALID) {
 #pragma unroll
-                for (int k = 0; k < 2; k++) {
+                for (int k = 0; k < (kFilter == JPT_FILTER_TRILINEAR ? 2 : 1); k++) {
                     if (k >= nf || foot[k].lw == 0) continue;
                     const LevelFoot &F = foot[k];
-                    if (filter == JPT_FILTER_NEAREST) {
-                        ids[4 * k] = block_of(F, F.x0, F.y0);
+                    if constexpr (kFilter == JPT_FILTER_NEAREST) {
+                        ids[0] = block_of(F, F.x0, F.y0);
                     } else {
                         const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
                         if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
@@ -106,21 +112,22 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
                     }
                 }
             }
-            // Distinct ids of the wave: take the first pending id of the first
-            // lane that has one, drop it everywhere, let that lane record it.
-            while (true) {
-                uint32_t cand = 0xFFFFFFFFu;
+            uint32_t left[kIds];
 #pragma unroll
-                for (int k = 7; k >= 0; k--)
-                    if (ids[k] != 0xFFFFFFFFu) cand = ids[k];
-                const uint64_t pending = __ballot(cand != 0xFFFFFFFFu);
-                if (pending == 0) break;
-                const int leader = __builtin_ctzll(pending);
-                const uint32_t id = __builtin_amdgcn_readlane(cand, leader);
+            for (int k = 0; k < kIds; k++) {
+                left[k] = __shfl_up(ids[k], 1, 64);
+                if (lane == 0) left[k] = 0xFFFFFFFFu;
+            }
 #pragma unroll
-                for (int k = 0; k < 8; k++)
-                    if (ids[k] == id) ids[k] = 0xFFFFFFFFu;
-                if ((int)lane == leader) set_insert(s_key, s_bits, vis, id);
+            for (int k = 0; k < kIds; k++) {
+                const uint32_t id = ids[k];
+                bool dup = id == 0xFFFFFFFFu;
+#pragma unroll
+                for (int j = 0; j < kIds; j++) {
+                    dup |= left[j] == id;
+                    if (j < k) dup |= ids[j] == id;
+                }
+                if (!dup) set_insert(s_key, s_bits, vis, id);
             }
         }
         __syncthreads();
@@ -134,6 +141,16 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
     if (__ballot(invalid) && lane == 0) atomicOr(&s_bad, 1u);
     __syncthreads();
     if (threadIdx.x == 0 && s_bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
+}
+
+template <uint32_t kFilter>
+void launch_mark(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame, hipStream_t st) {
+    if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
+        hipLaunchKernelGGL((k_mark<kFilter, true>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, frame->counters);
+    else
+        hipLaunchKernelGGL((k_mark<kFilter, false>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, frame->counters);
 }
 
 // Frame number of an LRU frame: the caller's, or the cache's own counter.
@@ -573,7 +590,6 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         HIP_CHECK_LAUNCH();
     }
     const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
-    const bool lds_desc = scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap;
     for (uint32_t v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
         ViewTable tab;
         make_view_table(views, v0, n_views - v0 < kMaxLaunchViews ? n_views - v0 : kMaxLaunchViews, kTileW, kTileH,
@@ -582,13 +598,9 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         uint32_t groups = tab.span;
         if (tuning && tuning->mark_groups && tuning->mark_groups < groups)
             groups = xcd ? (tuning->mark_groups + 7) / 8 * 8 : tuning->mark_groups;
-        if (lds_desc)
-            hipLaunchKernelGGL(k_mark<true>, dim3(groups), dim3(kMarkThreads), 0, st, scene->levels, scene->textures,
-                               scene->n_textures, scene->n_levels, tab, filter, frame->vis, frame->counters);
-        else
-            hipLaunchKernelGGL(k_mark<false>, dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                               scene->textures, scene->n_textures, scene->n_levels, tab, filter, frame->vis,
-                               frame->counters);
+        if (filter == JPT_FILTER_NEAREST) launch_mark<JPT_FILTER_NEAREST>(scene, tab, groups, frame, st);
+        else if (filter == JPT_FILTER_BILINEAR) launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, st);
+        else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, st);
         HIP_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis,

@@ -466,25 +466,27 @@ class Renderer:
         self.decode(stream)
         self.resolve(stream)
 
-    def capture(self, stream):
-        """The batched form: capture one frame of every view into a HIP graph
-        (jpt_graph_capture) on `stream`, a torch.cuda.Stream other than the
-        default one.  With an LRU cache the renderer switches to FRAME_AUTO."""
+    def capture(self, stream, views: "Views | None" = None):
+        """The batched form: capture one frame of every view (the renderer's,
+        or `views`) into a HIP graph (jpt_graph_capture) on `stream`, a
+        torch.cuda.Stream other than the default one.  With an LRU cache the
+        renderer switches to FRAME_AUTO."""
         if self.cache.policy == CACHE_LRU:
             self.frame_no = FRAME_AUTO
         self.frame.c.frame_no = self.frame_no
-        return Graph(self, stream)
+        return Graph(self, stream, views or self.views)
 
 
 class Graph:
     """A captured frame (jpt_graph); launch() replays it on its stream."""
 
-    def __init__(self, r: Renderer, stream):
+    def __init__(self, r: Renderer, stream, views: Views):
         self.r = r
+        self.views = views
         self.stream = stream
         h = vp()
         _check("jpt_graph_capture", lib().jpt_graph_capture(
-            ctypes.byref(r.scene.c), r.views.c, r.views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
+            ctypes.byref(r.scene.c), views.c, views.n, r.filter, ctypes.byref(r.frame.c), ctypes.byref(r.cache.c),
             r.idct_mode, ctypes.byref(r.tuning) if r.tuning else None, vp(stream.cuda_stream), ctypes.byref(h)))
         self.h = h
 

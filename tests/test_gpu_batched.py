@@ -111,3 +111,18 @@ def test_lru_graph_counts_frames(gpu):
         full, _, _ = osc.render(gb, wl.filter)
         assert parity.frame_diff(r.views.frame_host(), full) <= 1
     g.close()
+
+
+def test_autotuner_keeps_results_and_caches(gpu, tmp_path):
+    from paper_2510_08166_amd import jpt, tune
+    wl = configs.batched_small(seed=10)
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter)
+    r.render()
+    ref = tune.frame_digest(r)
+    path = str(tmp_path / "tune.json")
+    t = tune.tune(r, reps=3, cache_path=path)
+    r.render()
+    assert tune.frame_digest(r) == ref
+    r2 = jpt.Renderer(wl.textures, wl.views, wl.filter, host=r.host)
+    t2 = tune.tune(r2, cache_path=path)          # served from the cache file
+    assert tune.to_dict(t2) == tune.to_dict(t)
