@@ -26,6 +26,27 @@ sys.path.insert(0, ROOT)
 METRIC = "ms/frame visible-block decode+resolve @1080p; Mblocks/s; fwd+bwd ms; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic per launch of a phase's kernel on the 1080p frame, from
+# `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` (KiB per dispatch), each
+# scaled by what the same counter reads for one elementwise add of 1 GiB in
+# and 1 GiB out (fetch_scale, write_scale).  An entry holds only for the
+# kernel source it was measured on (sha256 prefix of the file); otherwise the
+# bench reports traffic as null.
+TRAFFIC = {}
+
+
+def source_sha(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(phase):
+    t = TRAFFIC.get(phase)
+    if not t or source_sha(t["file"]) != t["sha"]:
+        return None
+    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -196,7 +217,7 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
     dom_ms = float(med[PHASES.index(dom)])
     achieved = ab_phase[dom] / (dom_ms * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
             "algorithmic_bytes_per_launch": int(ab_phase[dom]), "avg_launch_ms": round(dom_ms, 4)}
     out = {
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms/frame", "n_gpus": 1,

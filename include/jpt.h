@@ -404,7 +404,7 @@ jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t
 /* Backward: dframe = dL/dframe_f -> dF = dL/dF.  dtexel is scratch of
  * n_slots x 768 int64 (texel gradients in fixed point, 2^-32 units, summed
  * with integer atomics so that the result does not depend on their order).
- * Errors: JPT_E_ARG, JPT_E_HIP. */
+ * Errors: JPT_E_ARG (also n_slots >= 2^24), JPT_E_HIP. */
 jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                         const jpt_frame *frame, const jpt_cache *cache, const float *dframe, int64_t *dtexel,
                         float *dF, uint32_t n_rows, void *stream);

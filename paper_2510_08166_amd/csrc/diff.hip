@@ -235,6 +235,33 @@ __global__ __launch_bounds__(256) void k_fwd_resolve(const jpt_level_desc *__res
     if (bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
 }
 
+// Backward of the resolve: every tap adds weight x dL/dpixel to its texel's
+// adjoint.  A workgroup takes a 64 x 16 pixel tile and first sums the adds of
+// the tile in an LDS table keyed by texel (neighbouring pixels share texels),
+// then flushes each touched texel with one global atomic per channel.  All
+// sums are 64-bit fixed point, so the result does not depend on the order.
+constexpr int kAccSize = 2048, kAccProbes = 8, kBwdRows = 4;
+
+__device__ __forceinline__ void acc_add(uint32_t *s_key, unsigned long long *s_val,
+                                        unsigned long long *__restrict__ dtexel, uint32_t addr, long long a0,
+                                        long long a1, long long a2) {
+    uint32_t h = (addr * 2654435761u) >> (32 - 11);
+    for (int p = 0; p < kAccProbes; p++) {
+        const uint32_t old = atomicCAS(s_key + h, 0xFFFFFFFFu, addr);
+        if (old == 0xFFFFFFFFu || old == addr) {
+            atomicAdd(s_val + 3 * h + 0, (unsigned long long)a0);
+            atomicAdd(s_val + 3 * h + 1, (unsigned long long)a1);
+            atomicAdd(s_val + 3 * h + 2, (unsigned long long)a2);
+            return;
+        }
+        h = (h + 1) & (kAccSize - 1);
+    }
+    unsigned long long *d = dtexel + (size_t)addr * 3;  // table crowded: straight to HBM
+    atomicAdd(d + 0, (unsigned long long)a0);
+    atomicAdd(d + 1, (unsigned long long)a1);
+    atomicAdd(d + 2, (unsigned long long)a2);
+}
+
 template <bool kLdsDesc>
 __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__restrict__ levels,
                                                      const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
@@ -245,26 +272,38 @@ __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__res
                                                      unsigned long long *__restrict__ dtexel) {
     __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
-    if constexpr (kLdsDesc) {
-        load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
-        __syncthreads();
+    __shared__ uint32_t s_key[kAccSize];
+    __shared__ unsigned long long s_val[3 * kAccSize];
+    if constexpr (kLdsDesc) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
+    for (int i = threadIdx.x; i < kAccSize; i += 256) s_key[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < 3 * kAccSize; i += 256) s_val[i] = 0ull;
+    __syncthreads();
+    const uint32_t x = blockIdx.x * 64 + (threadIdx.x & 63);
+    for (int r = 0; r < kBwdRows; r++) {
+        const uint32_t y = blockIdx.y * (4 * kBwdRows) + r * 4 + (threadIdx.x >> 6);
+        if (x >= W || y >= H) continue;
+        const jpt_gpixel px = gbuf[(size_t)y * pitch + x];
+        FTaps T;
+        int st;
+        if constexpr (kLdsDesc) st = float_taps(LdsDesc{s_t, s_l}, n_tex, px, filter, slot_of, T);
+        else st = float_taps(GlobalDesc{levels, texs}, n_tex, px, filter, slot_of, T);
+        if (st != PIX_VALID) continue;
+        const float *g = dframe + ((size_t)y * W + x) * 3;
+        const float g0 = g[0], g1 = g[1], g2 = g[2];
+        for (int k = 0; k < T.n; k++) {
+            if (T.slot[k] == JPT_SLOT_NONE) continue;
+            acc_add(s_key, s_val, dtexel, T.slot[k] * 256u + T.off[k], __float2ll_rn(g0 * T.w[k] * kFixScale),
+                    __float2ll_rn(g1 * T.w[k] * kFixScale), __float2ll_rn(g2 * T.w[k] * kFixScale));
+        }
     }
-    const uint32_t x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (x >= W || y >= H) return;
-    const jpt_gpixel px = gbuf[(size_t)y * pitch + x];
-    FTaps T;
-    int st;
-    if constexpr (kLdsDesc) st = float_taps(LdsDesc{s_t, s_l}, n_tex, px, filter, slot_of, T);
-    else st = float_taps(GlobalDesc{levels, texs}, n_tex, px, filter, slot_of, T);
-    if (st != PIX_VALID) return;
-    const float *g = dframe + ((size_t)y * W + x) * 3;
-    const float g0 = g[0], g1 = g[1], g2 = g[2];
-    for (int k = 0; k < T.n; k++) {
-        if (T.slot[k] == JPT_SLOT_NONE) continue;
-        unsigned long long *d = dtexel + (size_t)T.slot[k] * 768 + T.off[k] * 3;
-        atomicAdd(d + 0, (unsigned long long)__float2ll_rn(g0 * T.w[k] * kFixScale));
-        atomicAdd(d + 1, (unsigned long long)__float2ll_rn(g1 * T.w[k] * kFixScale));
-        atomicAdd(d + 2, (unsigned long long)__float2ll_rn(g2 * T.w[k] * kFixScale));
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAccSize; i += 256) {
+        const uint32_t a = s_key[i];
+        if (a == 0xFFFFFFFFu) continue;
+        unsigned long long *d = dtexel + (size_t)a * 3;
+        atomicAdd(d + 0, s_val[3 * i + 0]);
+        atomicAdd(d + 1, s_val[3 * i + 1]);
+        atomicAdd(d + 2, s_val[3 * i + 2]);
     }
 }
 
@@ -394,7 +433,7 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
                                    int64_t *dtexel, float *dF, uint32_t n_rows, void *stream) {
     jpt_status s = check(scene, views, n_views, filter, frame, cache);
     if (s) return s;
-    if (!dframe || !dtexel || !dF || cache->n_slots == 0) return JPT_E_ARG;
+    if (!dframe || !dtexel || !dF || cache->n_slots == 0 || cache->n_slots >= (1u << 24)) return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
     unsigned long long *dt = reinterpret_cast<unsigned long long *>(dtexel);
     hipLaunchKernelGGL(k_zero64, dim3(2048), dim3(256), 0, st, dt, (size_t)cache->n_slots * 768);
@@ -403,7 +442,7 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
     for (uint32_t v = 0; v < n_views; v++) {
         const jpt_view &V = views[v];
         if (!V.width || !V.height) continue;
-        dim3 grid((V.width + 63) / 64, (V.height + 3) / 4);
+        dim3 grid((V.width + 63) / 64, (V.height + 4 * kBwdRows - 1) / (4 * kBwdRows));
         if (desc_fits(scene))
             hipLaunchKernelGGL(k_bwd_resolve<true>, grid, dim3(256), 0, st, scene->levels, scene->textures,
                                scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
