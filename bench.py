@@ -298,7 +298,7 @@ def heavy_form(args, reps=None):
     from paper_2510_08166_amd import jpt
     from paper_2510_08166_amd.synth import configs
     t0 = time.perf_counter()
-    wl = configs.heavy()
+    wl = configs.heavy(log=log)
     log("heavy workload generated in %.1f s" % (time.perf_counter() - t0))
     slots = (2 << 30) // 1024
     t0 = time.perf_counter()
@@ -433,7 +433,7 @@ def main():
         label = ("1080p: 32 x 2048^2 textures (q50-90, 4:2:0, 8 levels), 1920x1080 G-buffer from 200 quads, "
                  "bilinear, no cache")
     else:
-        wl = configs.batched16()
+        wl = configs.batched16(log=log)
         label = ("batched: 16 views (2 stereo pairs 2064x2208 + 12 mono 1280x720..2560x1440) over a 128-texture "
                  "pool (512..4096, q50-90, 4:2:0), one graph launch per frame, bilinear, no cache")
     log("workload generated in %.1f s" % (time.perf_counter() - t0))

@@ -338,7 +338,7 @@ jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *c
  * (integer weights: bilinear (sum t*w + 32768) >> 16 per channel,
  * trilinear (a*(256-t) + b*t + 128) >> 8).  Background pixels get 0;
  * invalid pixels and taps in blocks without a slot get JPT_TEXEL_INVALID.
- * Errors: JPT_E_ARG, JPT_E_HIP. */
+ * Errors: JPT_E_ARG (also a cache of 0 slots), JPT_E_HIP. */
 jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                        const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
 
@@ -384,8 +384,10 @@ jpt_status jpt_graph_destroy(jpt_graph *graph);
  * unit of the item (4:2:0: Y0..Y3, Cb, Cr; 4:4:4: Y, Cb, Cr, then three zero
  * units).  Only the first min(items listed, max_items, n_rows) rows are read
  * or written: n_rows should be counters[JPT_CTR_ITEMS] of the frame.
- * texel_f: n_slots x 16 x 16 x 3 floats.  frame_f / dframe: the views'
- * pixels in order, width x height x 3 floats each, packed.  All pointers
+ * texel_f (and dtexel below): 16 x 16 x 3 entries per cache slot, for
+ * every slot up to the largest one a listed item uses (with
+ * JPT_CACHE_NONE: counters[JPT_CTR_NEW] slots).  frame_f / dframe: the
+ * views' pixels in order, width x height x 3 floats each, packed.  All pointers
  * are device memory owned by the caller; calls are asynchronous on `stream`.
  * ------------------------------------------------------------------ */
 
@@ -402,8 +404,9 @@ jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t
                          float *texel_f, float *frame_f, void *stream);
 
 /* Backward: dframe = dL/dframe_f -> dF = dL/dF.  dtexel is scratch of
- * n_slots x 768 int64 (texel gradients in fixed point, 2^-32 units, summed
- * with integer atomics so that the result does not depend on their order).
+ * 768 int64 per slot as texel_f (texel gradients in fixed point, 2^-32
+ * units, summed with integer atomics so that the result does not depend on
+ * their order); only the listed items' slots are cleared and used.
  * Errors: JPT_E_ARG (also n_slots >= 2^24), JPT_E_HIP. */
 jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                         const jpt_frame *frame, const jpt_cache *cache, const float *dframe, int64_t *dtexel,

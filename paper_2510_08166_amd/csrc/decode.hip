@@ -35,8 +35,6 @@ __device__ __forceinline__ int bsel(uint32_t c, int a, int b) { return b ^ ((a ^
 // ------------------------------------------------------------- entropy
 typedef const __attribute__((address_space(1))) uint32_t *gu32;
 
-constexpr int kWin = 48;  // words of each lane's MCU staged in LDS (1536 bits)
-
 // Codes longer than the fast-table index: canonical decoding (the first
 // length whose largest code is >= the prefix), returned in the fast-entry
 // format without the value, or JPT_FE_BAD for no code / an invalid symbol.
@@ -62,199 +60,199 @@ __device__ __noinline__ uint32_t slow_entry(const uint32_t *tab, uint32_t tsel, 
     return JPT_FE_BAD;
 }
 
-template <bool kLdsTables>
-__global__ __launch_bounds__(64) void k_entropy(const jpt_level_desc *__restrict__ levels,
-                                                const uint32_t *__restrict__ word_level,
-                                                const uint32_t *__restrict__ tables, uint32_t *__restrict__ work,
-                                                uint32_t *__restrict__ counters, int16_t *__restrict__ coef) {
-    __shared__ __attribute__((aligned(16))) uint32_t s_tab[kLdsTables ? JPT_TABLESET_WORDS : 4];
-    __shared__ __attribute__((aligned(16))) int16_t s_coef[64 * kItemCoefs];
-    __shared__ uint32_t s_win[kWin * 64];  // word i of lane l at i*64 + l
-    const uint32_t lane = threadIdx.x;
-    const uint32_t n_items = counters[JPT_CTR_ITEMS];
-    if (blockIdx.x * 64u >= n_items) return;
-    if constexpr (kLdsTables) {
-        // 18 KiB of tables: all 16-byte loads in flight before the LDS stores
-        constexpr int kVec = JPT_TABLESET_WORDS / 4 / 64;
-        static_assert(JPT_TABLESET_WORDS % 256 == 0, "table set must split into 64 lanes x uint4");
-        uint4 v[kVec];
-        const uint4 *src = reinterpret_cast<const uint4 *>(tables);
-#pragma unroll
-        for (int i = 0; i < kVec; i++) v[i] = src[i * 64 + lane];
-        uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
-#pragma unroll
-        for (int i = 0; i < kVec; i++) dst[i * 64 + lane] = v[i];
-    }
+// One table lookup of the symbol that starts at the top of `peek` in table
+// t (0 DC luma, 1 AC luma, 3 AC chroma), packed for the chain walk:
+// bits 0-4 bits the symbol takes with its appended bits (0: no valid code),
+// 5-8 run, 9-12 size, 16-31 the coefficient value (or DC difference).
+__device__ __forceinline__ uint32_t decode_at(const uint32_t *tab, uint32_t t, uint32_t thr, uint32_t peek) {
+    const uint32_t p16 = peek >> 16;
+    const uint32_t e1 = tab[t * JPT_FAST_SIZE + (peek >> (32 - JPT_FAST_BITS))];
+    const uint32_t e2 = tab[JPT_LONG_OFFSET + t * JPT_LONG_SIZE + min(p16 - thr, (uint32_t)JPT_LONG_SIZE - 1u)];
+    uint32_t e = p16 >= thr ? e2 : e1;
+    if ((e & 31u) == 0 && !(e & JPT_FE_BAD)) e = slow_entry(tab, t, peek);
+    const uint32_t len = e & 31u, size = (e >> 6) & 15u, run = (e >> 10) & 15u;
+    const uint32_t fused = (e >> 5) & 1u;
+    const uint32_t extra = (uint32_t)(((uint64_t)(peek << len) << size) >> 32);
+    const uint32_t lim = (1u << size) >> 1;
+    const int vn = (int)extra - (int)(extra < lim ? (1u << size) - 1u : 0u);
+    const int value = bsel(fused, (int)e >> 16, vn);
+    const uint32_t used = len + (fused ? 0u : size);
+    const bool bad = len == 0 || (e & JPT_FE_BAD);
+    return bad ? 0u : (used | (run << 5) | (size << 9) | ((uint32_t)value << 16));
+}
 
-    for (uint32_t chunk = blockIdx.x; chunk * 64u < n_items; chunk += gridDim.x) {
-        int4 *z = reinterpret_cast<int4 *>(s_coef);
-        for (uint32_t i = lane; i < 64u * kItemCoefs / 8u; i += 64) z[i] = make_int4(0, 0, 0, 0);
-        const uint32_t item = chunk * 64u + lane;
-        // ---- locate the MCU: level, record, bit span, absolute DCs
-        bool active = false;
-        uint32_t w = 0, sampling = 0, start = 0, end = 0, limit = 0, wbase = 0;
-        int dc0 = 0, dc1 = 0, dc2 = 0;
-        gu32 stream = nullptr;
-        const uint32_t *tab = kLdsTables ? s_tab : tables;
-        if (item < n_items) {
-            w = work[item];
-            const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
-            const jpt_level_desc *L = levels + word_level[b >> 5];
-            const uint32_t blk_base = L->blk_base, blk_cols = L->blk_cols, mcu_cols = L->mcu_cols;
-            const uint32_t n_mcu = L->n_mcu;
-            sampling = L->sampling;
-            stream = (gu32)L->stream;
-            const gu32 recs = (gu32)L->records;
-            const uint32_t stream_bits = (uint32_t)L->stream_bits;
-            if constexpr (!kLdsTables) tab = tables + (size_t)L->table_set * JPT_TABLESET_WORDS;
-            const uint32_t r = b - blk_base, by = r / blk_cols, bx = r - by * blk_cols;
-            uint32_t mcu;
-            active = true;
-            if (sampling == JPT_SAMPLING_444) {
-                const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
-                active = mx < mcu_cols && my < n_mcu / mcu_cols;
-                mcu = my * mcu_cols + mx;
-            } else {
-                mcu = by * mcu_cols + bx;
-            }
-            if (active) {
-                // the five record words this MCU needs, loaded together from
-                // in-bounds addresses (word 16 is the next record's anchor, read
-                // only when that record exists)
-                const uint32_t g = mcu / 9, j = mcu - g * 9;
-                const gu32 rec = recs + (size_t)g * 16;
-                const bool last = mcu + 1 >= n_mcu;
-                const uint32_t i1 = j ? 1 + ((j - 1) >> 1) : 0u;
-                const uint32_t i2 = last ? 0u : (j < 8 ? 1 + (j >> 1) : 16u);
-                const uint32_t bp = 160 + 36 * j;
-                const uint32_t anchor = rec[0], w1 = rec[i1], w2 = rec[i2];
-                const uint32_t d0 = rec[bp >> 5], d1 = rec[(bp >> 5) + 1];
-                const uint32_t rel = j ? (w1 >> (((j - 1) & 1) * 16)) & 0xFFFFu : 0u;
-                start = anchor + rel;
-                end = last ? stream_bits : (j < 8 ? anchor + ((w2 >> ((j & 1) * 16)) & 0xFFFFu) : w2);
-                const uint64_t dv = ((((uint64_t)d1) << 32) | d0) >> (bp & 31);
-                dc0 = sext12((uint32_t)dv & 0xFFFu);
-                dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu);
-                dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
-                limit = (uint32_t)JPT_STREAM_WORDS(stream_bits);
-                wbase = (start >> 5) & ~3u;
-            }
-        }
-        // ---- stage the first kWin words of each MCU into LDS (16-byte loads, all in flight)
-        {
-            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-            typedef const __attribute__((address_space(1))) u32x4 *gu32x4;
-            // unconditional loads from clamped in-bounds addresses (the stream
-            // holds at least 4 words), zeroed afterwards, so that no branch
-            // forces a wait between them
-            u32x4 v[kWin / 4];
-            const uint32_t last = limit >= 4u ? limit - 4u : 0u;
-            const gu32 src = active ? stream : (gu32)tables;  // any valid 16-byte aligned address
-#pragma unroll
-            for (int i = 0; i < kWin / 4; i++) {
-                const uint32_t wi = wbase + 4 * i;
-                v[i] = *(gu32x4)(src + (active ? min(wi, last) : 0u));
-            }
-#pragma unroll
-            for (int i = 0; i < kWin / 4; i++) {
-                const bool ok = active && wbase + 4 * i < limit;
-                s_win[(4 * i + 0) * 64 + lane] = ok ? v[i].x : 0u;
-                s_win[(4 * i + 1) * 64 + lane] = ok ? v[i].y : 0u;
-                s_win[(4 * i + 2) * 64 + lane] = ok ? v[i].z : 0u;
-                s_win[(4 * i + 3) * 64 + lane] = ok ? v[i].w : 0u;
-            }
-        }
+// k_entropy: one wavefront per MCU.  Per step the wave covers the next 64
+// bit positions of the MCU's stream: lane i decodes, from its own bit offset
+// i, the symbol that would start there under each of the three tables the
+// MCU can be in (DC luma, AC luma, AC chroma), all lookups in flight at
+// once.  The scalar unit then walks the true symbol chain through these
+// speculative decodes (readlane of the lane at the current offset), applies
+// the decoder state (data unit, zigzag position, Y DC predictor) and hands
+// each coefficient back to the lane that decoded it; those lanes write them
+// to the MCU's LDS tile in one store.  About a dozen symbols per step
+// instead of one.  The MCU's first 128 words sit in two VGPRs across the
+// wave and reach the scalar unit by readlane.
+constexpr int kEntWaves = 4;  // MCUs in flight per workgroup
+
+// Orders the LDS accesses of one wavefront before and after this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool kLdsTables>
+__global__ __launch_bounds__(64 * kEntWaves) void k_entropy(const jpt_level_desc *__restrict__ levels,
+                                                            const uint32_t *__restrict__ word_level,
+                                                            const uint32_t *__restrict__ tables,
+                                                            uint32_t *__restrict__ work,
+                                                            uint32_t *__restrict__ counters,
+                                                            int16_t *__restrict__ coef) {
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[kLdsTables ? JPT_TABLESET_WORDS : 4];
+    __shared__ __attribute__((aligned(16))) int16_t s_coef[kEntWaves][kItemCoefs];
+    // the wave index is uniform over the wave: say so, so that the MCU state
+    // lives in scalar registers and the chain walk runs on the scalar unit
+    const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t n_items = counters[JPT_CTR_ITEMS];
+    if (blockIdx.x * (uint32_t)kEntWaves >= n_items) return;
+    if constexpr (kLdsTables) {
+        static_assert(JPT_TABLESET_WORDS % 4 == 0, "table set must split into uint4");
+        const uint4 *src = reinterpret_cast<const uint4 *>(tables);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_tab);
+#pragma unroll 7
+        for (int i = threadIdx.x; i < JPT_TABLESET_WORDS / 4; i += 64 * kEntWaves) dst[i] = src[i];
         __syncthreads();
+    }
+    int16_t *cf = s_coef[wv];
+    for (uint32_t item = blockIdx.x * kEntWaves + wv; item < n_items; item += gridDim.x * kEntWaves) {
+        // ---- locate the MCU (all wave-uniform): level, record, bit span, absolute DCs
+        const uint32_t w = work[item];
+        const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
+        const jpt_level_desc *L = levels + word_level[b >> 5];
+        const uint32_t blk_base = L->blk_base, blk_cols = L->blk_cols, mcu_cols = L->mcu_cols;
+        const uint32_t n_mcu = L->n_mcu;
+        const bool s444 = L->sampling == JPT_SAMPLING_444;
+        const gu32 stream = (gu32)L->stream;
+        const gu32 recs = (gu32)L->records;
+        const uint32_t stream_bits = (uint32_t)L->stream_bits;
+        const uint32_t *tab = kLdsTables ? s_tab : tables + (size_t)L->table_set * JPT_TABLESET_WORDS;
+        const uint32_t r = b - blk_base, by = r / blk_cols, bx = r - by * blk_cols;
+        uint32_t mcu;
+        bool active = true;
+        if (s444) {
+            const uint32_t mx = 2 * bx + (q & 1), my = 2 * by + (q >> 1);
+            active = mx < mcu_cols && my < n_mcu / mcu_cols;
+            mcu = my * mcu_cols + mx;
+        } else {
+            mcu = by * mcu_cols + bx;
+        }
+        // zero the coefficient tile (48 lanes x 16 bytes)
+        if (lane < kItemCoefs / 8) reinterpret_cast<int4 *>(cf)[lane] = make_int4(0, 0, 0, 0);
+        wave_sync();
+        bool ok = true;
         if (active) {
-            int16_t *cf = s_coef + lane * kItemCoefs;
-            uint32_t wp = start >> 5;
-            const uint32_t sh0 = start & 31;
-            auto word_at = [&](uint32_t wi) -> uint32_t {  // the LDS window, then HBM past its end
-                const uint32_t off = wi - wbase;
-                if (off < (uint32_t)kWin) return s_win[off * 64 + lane];
-                return wi < limit ? stream[wi] : 0u;
-            };
-            uint64_t buf = ((((uint64_t)word_at(wp)) << 32) | word_at(wp + 1)) << sh0;
-            int nb = 64 - (int)sh0;  // valid bits in buf, >= 32 at the top of every iteration
-            wp += 2;
-            uint32_t pos = start;
-            const bool s444 = sampling == JPT_SAMPLING_444;
-            const int ndu = s444 ? 3 : 6;
-            uint32_t thr[4];  // start of the long-code region of each table
+            const uint32_t g = mcu / 9, j = mcu - g * 9;
+            const gu32 rec = recs + (size_t)g * 16;
+            const bool last = mcu + 1 >= n_mcu;
+            const uint32_t i1 = j ? 1 + ((j - 1) >> 1) : 0u;
+            const uint32_t i2 = last ? 0u : (j < 8 ? 1 + (j >> 1) : 16u);
+            const uint32_t bp = 160 + 36 * j;
+            const uint32_t anchor = rec[0], w1 = rec[i1], w2 = rec[i2];
+            const uint32_t d0 = rec[bp >> 5], d1 = rec[(bp >> 5) + 1];
+            const uint32_t start = anchor + (j ? (w1 >> (((j - 1) & 1) * 16)) & 0xFFFFu : 0u);
+            const uint32_t end = last ? stream_bits : (j < 8 ? anchor + ((w2 >> ((j & 1) * 16)) & 0xFFFFu) : w2);
+            const uint64_t dv = ((((uint64_t)d1) << 32) | d0) >> (bp & 31);
+            const int dc0 = sext12((uint32_t)dv & 0xFFFu);
+            const int dc1 = sext12((uint32_t)(dv >> 12) & 0xFFFu);
+            const int dc2 = sext12((uint32_t)(dv >> 24) & 0xFFFu);
+            const uint32_t limit = (uint32_t)JPT_STREAM_WORDS(stream_bits);
+            // the MCU's words: word wbase + i in lane i of mw0 (i < 64) / mw1 (64 + i)
+            const uint32_t wbase = start >> 5;
+            const uint32_t mw0 = stream[min(wbase + lane, limit - 1u)];
+            const uint32_t mw1 = stream[min(wbase + 64u + lane, limit - 1u)];
+            uint32_t thr[4];
 #pragma unroll
             for (int t = 0; t < 4; t++) thr[t] = tab[JPT_SLOW_OFFSET + t * JPT_SLOW_WORDS + JPT_SLOW_T];
-            // the absolute DCs from the record
-            cf[0] = (int16_t)dc0;
-            cf[(s444 ? 1 : 4) * 64] = (int16_t)dc1;
-            cf[(s444 ? 2 : 5) * 64] = (int16_t)dc2;
+            wave_sync();  // the tile is zeroed before the DCs go in
+            if (lane == 0) {
+                cf[0] = (int16_t)dc0;
+                cf[(s444 ? 1 : 4) * 64] = (int16_t)dc1;
+                cf[(s444 ? 2 : 5) * 64] = (int16_t)dc2;
+            }
+            const int ndu = s444 ? 3 : 6;
+            uint32_t pos = start;
             int du = 0, k = 1, ypred = dc0;
-            uint32_t toff1 = 1 * JPT_FAST_SIZE, toff2 = JPT_LONG_OFFSET + 1 * JPT_LONG_SIZE, Tcur = thr[1];
-            bool err = false, done = false;
-            // One symbol per iteration, written as straight-line code with
-            // selects; the refill word is read from LDS before it is known to
-            // be needed so that its latency overlaps the table lookups.
-            for (int it = 0; it < 6 * 64 + 8; ++it) {
-                if (done || err) break;
-                const uint32_t off = wp - wbase;
-                uint32_t wnext = s_win[min(off, (uint32_t)kWin - 1u) * 64 + lane];
-                const uint32_t peek = (uint32_t)(buf >> 32);
-                // short codes from the 10-bit table, long ones from the table over
-                // [T, 65536) of the 16-bit prefix space: both reads in flight together
-                const uint32_t p16 = peek >> 16;
-                const uint32_t li = min(p16 - Tcur, (uint32_t)JPT_LONG_SIZE - 1u);
-                const uint32_t e1 = tab[toff1 + (peek >> (32 - JPT_FAST_BITS))];
-                const uint32_t e2 = tab[toff2 + li];
-                uint32_t e = p16 >= Tcur ? e2 : e1;
-                if ((e & 31u) == 0 && !(e & JPT_FE_BAD)) e = slow_entry(tab, toff1 >> 10, peek);
-                const uint32_t len = e & 31u, size = (e >> 6) & 15u, run = (e >> 10) & 15u;
-                const uint32_t fused = (e >> 5) & 1u;
-                // appended bits (0 when size is 0) and their EXTEND
-                const uint32_t extra = (uint32_t)(((uint64_t)(peek << len) << size) >> 32);
-                const uint32_t lim = (1u << size) >> 1;
-                const int vn = (int)extra - (int)(extra < lim ? (1u << size) - 1u : 0u);
-                const int value = bsel(fused, (int)e >> 16, vn);
-                const uint32_t used = len + (fused ? 0u : size);
-                buf <<= used;
-                nb -= (int)used;
-                pos += used;
-                // state: k = next zigzag position of data unit du (0: a Y difference DC follows)
-                const uint32_t is_dc = k == 0;
-                const int kr = k + (int)run;
-                ypred += is_dc ? value : 0;
-                const uint32_t write = is_dc | (size != 0);
-                const int wpos = bsel(is_dc, 0, kr);
-                const int after_zero = bsel(run == 15, k + 16, 64);           // ZRL / EOB
-                const int nk = bsel(is_dc, 1, bsel(size != 0, kr + 1, after_zero));
-                err = (len == 0) | ((write != 0) & (wpos > 63)) | (nk > 64) | ((uint32_t)(ypred + 32768) > 65535u);
-                if (write && !err) cf[du * 64 + wpos] = (int16_t)bsel(is_dc, ypred, value);
-                const bool next_du = nk == 64;
-                du += next_du ? 1 : 0;
-                done = du >= ndu;
-                const bool chroma = s444 ? du != 0 : du >= 4;
-                k = next_du ? (chroma ? 1 : 0) : nk;
-                const uint32_t tsel = (chroma ? 2u : 0u) + (k != 0 ? 1u : 0u);
-                toff1 = tsel * JPT_FAST_SIZE;
-                toff2 = JPT_LONG_OFFSET + tsel * JPT_LONG_SIZE;
-                Tcur = (tsel & 2) ? ((tsel & 1) ? thr[3] : thr[2]) : ((tsel & 1) ? thr[1] : thr[0]);
-                // refill to >= 32 valid bits
-                const bool need = nb < 32;
-                if (need && off >= (uint32_t)kWin) wnext = wp < limit ? stream[wp] : 0u;
-                const uint64_t add = (uint64_t)wnext << ((32 - nb) & 63);
-                buf |= need ? add : 0ull;
-                nb += need ? 32 : 0;
-                wp += need ? 1u : 0u;
+            bool done = false, err = false;
+            // every step consumes at least one symbol of >= 1 bit
+            for (uint32_t step = 0; !done && !err; step++) {
+                if (pos > end || step > (end - start) + 1u) { err = true; break; }
+                // the 128 bits from word pos/32 on; lane i starts at bit (pos & 31) + i
+                const uint32_t wi = (pos >> 5) - wbase;
+                uint32_t W[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const uint32_t x = wi + i;
+                    W[i] = x < 64u ? __builtin_amdgcn_readlane(mw0, x)
+                                   : (x < 128u ? __builtin_amdgcn_readlane(mw1, x - 64u)
+                                               : stream[min(wbase + x, limit - 1u)]);
+                }
+                const uint32_t bit = (pos & 31u) + lane;  // 0..94
+                const uint32_t hi = bit < 32u ? W[0] : (bit < 64u ? W[1] : W[2]);
+                const uint32_t lo = bit < 32u ? W[1] : (bit < 64u ? W[2] : W[3]);
+                const uint32_t peek = (uint32_t)(((((uint64_t)hi) << 32) | lo) << (bit & 31u) >> 32);
+                const uint32_t pA = decode_at(tab, 1, thr[1], peek);
+                const uint32_t pD = decode_at(tab, 0, thr[0], peek);
+                const uint32_t pC = decode_at(tab, 3, thr[3], peek);
+                // ---- the chain walk (scalar)
+                uint32_t o = 0, wpos = 0xFFFFFFFFu;
+                int wval = 0;
+                while (o < 64u) {
+                    const bool chroma = s444 ? du != 0 : du >= 4;
+                    const uint32_t e = chroma ? __builtin_amdgcn_readlane(pC, o)
+                                              : (k == 0 ? __builtin_amdgcn_readlane(pD, o)
+                                                        : __builtin_amdgcn_readlane(pA, o));
+                    const uint32_t used = e & 31u, run = (e >> 5) & 15u, size = (e >> 9) & 15u;
+                    const int value = (int)e >> 16;
+                    if (used == 0) { err = true; break; }
+                    int nk, at = -1, val = 0;
+                    if (k == 0) {  // DC difference of Y1..Y3
+                        ypred += value;
+                        if ((uint32_t)(ypred + 32768) > 65535u) { err = true; break; }
+                        at = 0; val = ypred; nk = 1;
+                    } else if (size != 0) {
+                        at = k + (int)run; val = value; nk = at + 1;
+                        if (at > 63) { err = true; break; }
+                    } else {
+                        nk = run == 15 ? k + 16 : 64;  // ZRL / EOB
+                    }
+                    if (nk > 64) { err = true; break; }
+                    if (at >= 0 && lane == o) {  // the lane that decoded this symbol stores it
+                        wpos = (uint32_t)(du * 64 + at);
+                        wval = val;
+                    }
+                    o += used;
+                    k = nk;
+                    if (k == 64) {
+                        du++;
+                        if (du >= ndu) { done = true; break; }
+                        k = (s444 ? du != 0 : du >= 4) ? 1 : 0;
+                    }
+                }
+                if (wpos != 0xFFFFFFFFu) cf[wpos] = (int16_t)wval;
+                pos += o;
             }
-            if (!(done && !err && pos == end)) {
-                atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CORRUPT);
-                atomicMin(counters + JPT_CTR_ERROR_ITEM, item);
-                work[item] = w | 0x80000000u;
-            }
+            ok = done && !err && pos == end;
         }
-        __syncthreads();
-        const uint32_t n_valid = min(64u, n_items - chunk * 64u);
-        int4 *dst = reinterpret_cast<int4 *>(coef + (size_t)chunk * 64u * kItemCoefs);
-        for (uint32_t i = lane; i < n_valid * (kItemCoefs / 8u); i += 64) dst[i] = z[i];
-        __syncthreads();
+        // ---- publish
+        if (!ok && lane == 0) {
+            atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CORRUPT);
+            atomicMin(counters + JPT_CTR_ERROR_ITEM, item);
+            work[item] = w | 0x80000000u;
+        }
+        wave_sync();
+        if (lane < kItemCoefs / 8)
+            reinterpret_cast<int4 *>(coef + (size_t)item * kItemCoefs)[lane] = reinterpret_cast<const int4 *>(cf)[lane];
+        wave_sync();  // the tile is read before the next MCU clears it
     }
 }
 
@@ -580,17 +578,17 @@ __global__ __launch_bounds__(64) void k_idct_scalar(const jpt_level_desc *__rest
 
 uint32_t default_groups(const jpt_tuning *t, bool idct) {
     uint32_t g = t ? (idct ? t->idct_groups : t->decode_groups) : 0u;
-    return g ? g : (idct ? 2048u : 512u);
+    return g ? g : (idct ? 2048u : 1024u);
 }
 
 jpt_status launch_entropy(const jpt_scene *scene, jpt_frame *frame, const jpt_tuning *tuning, hipStream_t st) {
     const uint32_t groups = default_groups(tuning, false);
     if (scene->n_tablesets == 1)
-        hipLaunchKernelGGL(k_entropy<true>, dim3(groups), dim3(64), 0, st, scene->levels, scene->word_level,
-                           scene->tables, frame->work, frame->counters, frame->coef);
+        hipLaunchKernelGGL(k_entropy<true>, dim3(groups), dim3(64 * kEntWaves), 0, st, scene->levels,
+                           scene->word_level, scene->tables, frame->work, frame->counters, frame->coef);
     else
-        hipLaunchKernelGGL(k_entropy<false>, dim3(groups), dim3(64), 0, st, scene->levels, scene->word_level,
-                           scene->tables, frame->work, frame->counters, frame->coef);
+        hipLaunchKernelGGL(k_entropy<false>, dim3(groups), dim3(64 * kEntWaves), 0, st, scene->levels,
+                           scene->word_level, scene->tables, frame->work, frame->counters, frame->coef);
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }

@@ -21,10 +21,16 @@ struct LevelFoot {
 
 enum { PIX_BACKGROUND = 0, PIX_VALID = 1, PIX_INVALID = -1 };
 
-JPT_DEV uint32_t wrap(int v, uint32_t n) {
-    if ((n & (n - 1)) == 0) return (uint32_t)v & (n - 1);   // power of two: two's complement mask
-    int r = v % (int)n;
+// Non-negative v mod n for sizes that are not powers of two: an out-of-line
+// call, so that the common power-of-two case costs no division code.
+__device__ __noinline__ uint32_t wrap_general(int v, uint32_t n) {
+    const int r = v % (int)n;
     return (uint32_t)(r < 0 ? r + (int)n : r);
+}
+
+JPT_DEV uint32_t wrap(int v, uint32_t n) {
+    if (__builtin_expect((n & (n - 1)) == 0, 1)) return (uint32_t)v & (n - 1);  // two's complement mask
+    return wrap_general(v, n);
 }
 
 // Texel coordinate along one axis.  Returns false for a non-finite value or
@@ -42,9 +48,8 @@ JPT_DEV bool axis(float u, uint32_t n, bool linear, uint32_t &x0, uint32_t &x1, 
     } else {
         f = 0;
     }
-    int xi = (int)fl;
-    x0 = wrap(xi, n);
-    x1 = wrap(xi + 1, n);
+    x0 = wrap((int)fl, n);
+    x1 = x0 + 1 == n ? 0u : x0 + 1;  // (x + 1) mod n
     return true;
 }
 

@@ -367,8 +367,24 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void k_zero64(unsigned long long *__restrict__ p, size_t n) {
-    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0ull;
+// Clear the texel adjoints of the listed items' slots (a block's 16 x 16 x 3
+// entries once: by its 4:2:0 item, or by quadrant 0 of a 4:4:4 block).
+__global__ __launch_bounds__(256) void k_zero_items(const jpt_level_desc *__restrict__ levels,
+                                                    const uint32_t *__restrict__ word_level,
+                                                    const uint32_t *__restrict__ work,
+                                                    const uint32_t *__restrict__ counters,
+                                                    const uint32_t *__restrict__ slot_of,
+                                                    unsigned long long *__restrict__ dtexel, uint32_t max_items) {
+    const uint32_t n_items = min(counters[JPT_CTR_ITEMS], max_items);
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint32_t w = work[it];
+        const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
+        if (q != 0) continue;
+        const uint32_t slot = slot_of[b];
+        if (slot == JPT_SLOT_NONE) continue;
+        unsigned long long *d = dtexel + (size_t)slot * 768;
+        for (uint32_t i = threadIdx.x; i < 768; i += 256) d[i] = 0ull;
+    }
 }
 
 bool desc_fits(const jpt_scene *s) { return s->n_textures <= kLdsTexCap && s->n_levels <= kLdsLevCap; }
@@ -436,7 +452,8 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
     if (!dframe || !dtexel || !dF || cache->n_slots == 0 || cache->n_slots >= (1u << 24)) return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
     unsigned long long *dt = reinterpret_cast<unsigned long long *>(dtexel);
-    hipLaunchKernelGGL(k_zero64, dim3(2048), dim3(256), 0, st, dt, (size_t)cache->n_slots * 768);
+    hipLaunchKernelGGL(k_zero_items, dim3(2048), dim3(256), 0, st, scene->levels, scene->word_level, frame->work,
+                       frame->counters, cache->slot_of, dt, row_limit(frame, n_rows));
     HIP_CHECK_LAUNCH();
     size_t off = 0;
     for (uint32_t v = 0; v < n_views; v++) {

@@ -70,9 +70,13 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
         if (!tile_of(tab, slot, view, tx, ty)) continue;  // uniform over the workgroup
         const jpt_gpixel *__restrict__ gbuf = tab.v[view].gbuf;
         const uint32_t W = tab.v[view].width, H = tab.v[view].height, pitch = tab.v[view].pitch;
-        const uint32_t x = tx * kTileW + lane, y0 = ty * kTileH + wv;
-        jpt_gpixel nxt = (x < W && y0 < H) ? gbuf[(size_t)y0 * pitch + x]
-                                           : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+        const uint32_t x = tx * kTileW + lane, y0 = ty * kTileH + wv, xc = min(x, W - 1u);
+        // loads from clamped in-bounds addresses (no branch), masked afterwards
+        auto load_px = [&](uint32_t y) -> jpt_gpixel {
+            const jpt_gpixel g = gbuf[(size_t)min(y, H - 1u) * pitch + xc];
+            return (x < W && y < H) ? g : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+        };
+        jpt_gpixel nxt = load_px(y0);
         for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
             s_key[i] = 0xFFFFFFFFu;
             s_bits[i] = 0;
@@ -81,10 +85,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
 #pragma unroll 1
         for (int r = 0; r < kRows; r++) {
             const jpt_gpixel px = nxt;
-            const uint32_t yn = y0 + (r + 1) * (kMarkThreads / 64);
-            if (r + 1 < kRows)
-                nxt = (x < W && yn < H) ? gbuf[(size_t)yn * pitch + x]
-                                        : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+            if (r + 1 < kRows) nxt = load_px(y0 + (r + 1) * (kMarkThreads / 64));
             uint32_t ids[kIds];
 #pragma unroll
             for (int k = 0; k < kIds; k++) ids[k] = 0xFFFFFFFFu;

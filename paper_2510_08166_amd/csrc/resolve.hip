@@ -87,11 +87,14 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
         const uint32_t W = tab.v[view].width, H = tab.v[view].height, pitch = tab.v[view].pitch;
         const uint32_t frame_pitch = tab.v[view].frame_pitch;
         const uint32_t x = tx * kTileW + lane;
+        // loads from clamped in-bounds addresses, no branches: all rows in flight
         jpt_gpixel px[kRows];
+        const uint32_t xc = min(x, W - 1u);
 #pragma unroll
         for (int r = 0; r < kRows; r++) {
             const uint32_t y = ty * kTileH + wv + r * (kThreads / 64);
-            px[r] = (x < W && y < H) ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+            const jpt_gpixel g = gbuf[(size_t)min(y, H - 1u) * pitch + xc];
+            px[r] = (x < W && y < H) ? g : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
         }
         for (int r = 0; r < kRows; r++) {
             const uint32_t y = ty * kTileH + wv + r * (kThreads / 64);
@@ -101,12 +104,13 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
             if constexpr (kLdsDesc) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
             else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
             // all slot lookups of the pixel, then all texel loads
+            // unused taps read block 0 / slot 0 (valid addresses) and get weight 0
             uint32_t slot[kTaps], tex[kTaps];
 #pragma unroll
-            for (int t = 0; t < kTaps; t++) slot[t] = T.w[t] ? slot_of[T.blk[t]] : 0u;
+            for (int t = 0; t < kTaps; t++) slot[t] = slot_of[T.blk[t]];
 #pragma unroll
             for (int t = 0; t < kTaps; t++)
-                tex[t] = (T.w[t] && slot[t] != JPT_SLOT_NONE) ? texels[(size_t)slot[t] * 256 + T.off[t]] : 0u;
+                tex[t] = texels[(size_t)(slot[t] != JPT_SLOT_NONE ? slot[t] : 0u) * 256 + T.off[t]];
             if (x >= W || y >= H) continue;
             uint32_t out;
             if (st == PIX_BACKGROUND) {
@@ -165,7 +169,8 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
                                   const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning,
                                   void *stream) {
     (void)frame;
-    if (!scene || (n_views && !views) || !cache || !cache->slot_of || !cache->texels) return JPT_E_ARG;
+    if (!scene || (n_views && !views) || !cache || !cache->slot_of || !cache->texels || cache->n_slots == 0)
+        return JPT_E_ARG;
     if (filter > JPT_FILTER_TRILINEAR || !scene->levels || !scene->textures) return JPT_E_ARG;
     for (uint32_t v = 0; v < n_views; v++)
         if (!views[v].gbuf || !views[v].frame || views[v].pitch < views[v].width ||

@@ -518,19 +518,26 @@ class DiffFrame:
     def __init__(self, r: "Renderer"):
         if r.cache.policy != CACHE_NONE:
             raise ValueError("the differentiable form needs a frame-local cache (JPT_CACHE_NONE)")
-        torch = _torch()
         self.r = r
-        d = r.scene.device
-        n = max(1, r.cache.n_slots)
-        self.texel_f = torch.empty(n * 768, dtype=torch.float32, device=d)
-        self.dtexel = torch.empty(n * 768, dtype=torch.int64, device=d)
+        self.texel_f = self.dtexel = None
         self.n_pixels = r.views.n_pixels
+
+    def _scratch(self):
+        """Float texels and texel adjoints for the frame's new blocks (their
+        slots are 0 .. counters[CTR_NEW] - 1 in a frame-local cache)."""
+        torch = _torch()
+        n = max(1, min(int(self.r.frame.counters_host()[CTR_NEW]), self.r.cache.n_slots))
+        if self.texel_f is None or self.texel_f.numel() < n * 768:
+            d = self.r.scene.device
+            self.texel_f = torch.empty(n * 768, dtype=torch.float32, device=d)
+            self.dtexel = torch.empty(n * 768, dtype=torch.int64, device=d)
 
     def n_items(self) -> int:
         return int(self.r.frame.counters_host()[CTR_ITEMS])
 
     def dequantize(self, stream=None):
         torch = _torch()
+        self._scratch()
         F = torch.empty((self.n_items(), ITEMS_DU, 64), dtype=torch.float32, device=self.r.scene.device)
         if F.numel():
             _check("jpt_dequantize", lib().jpt_dequantize(ctypes.byref(self.r.scene.c), ctypes.byref(self.r.frame.c),
@@ -539,6 +546,8 @@ class DiffFrame:
 
     def forward(self, F, stream=None):
         torch = _torch()
+        if self.texel_f is None:
+            self._scratch()
         F = F.contiguous()
         self._check_F(F)
         frame_f = torch.empty((self.n_pixels, 3), dtype=torch.float32, device=F.device)
@@ -551,6 +560,8 @@ class DiffFrame:
 
     def backward(self, dframe, F_shape, stream=None):
         torch = _torch()
+        if self.dtexel is None:
+            self._scratch()
         dframe = dframe.contiguous().float()
         if tuple(dframe.shape) != (self.n_pixels, 3):
             raise ValueError("dframe shape %s" % (tuple(dframe.shape),))

@@ -223,14 +223,20 @@ def make_texture(seed: int, w: int, h: int, quality: int, sampling: int, n_level
     return EncodedTexture(tex_id, w, h, quality, sampling, jpegs, levels if keep_rgb else None)
 
 
-def make_textures(specs, keep_rgb=False, threads: int | None = None):
+def make_textures(specs, keep_rgb=False, threads: int | None = None, log=None):
     """specs: list of (seed, w, h, quality, sampling, n_levels).  Runs the C
-    generators on a thread pool (ctypes releases the GIL)."""
+    generators on a thread pool (ctypes releases the GIL).  `log` (optional)
+    is called with a progress line every 16 textures."""
     threads = threads or min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(threads) as ex:
         futs = [ex.submit(make_texture, s, w, h, q, smp, nl, keep_rgb, i)
                 for i, (s, w, h, q, smp, nl) in enumerate(specs)]
-        return [f.result() for f in futs]
+        out = []
+        for i, f in enumerate(futs):
+            out.append(f.result())
+            if log and (i + 1) % 16 == 0:
+                log("textures %d / %d" % (i + 1, len(futs)))
+        return out
 
 
 def seed_ints(seed: int, n: int) -> list[int]:

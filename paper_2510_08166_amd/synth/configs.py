@@ -94,7 +94,7 @@ def drift_transforms(rng: np.random.Generator, W: int, H: int, n_frames: int):
 
 
 def heavy(seed=3, n_tex=256, sides=(512, 1024, 2048, 4096, 8192), q_lo=40, q_hi=95, W=3840, H=2160, n_quads=2000,
-          n_frames=8, keep_rgb=False, name=None) -> Workload:
+          n_frames=8, keep_rgb=False, name=None, log=None) -> Workload:
     """Heavy recipe: textures of random power-of-two sides, q ~ U{q_lo..q_hi},
     4:2:0 / 4:4:4 half and half, full mip chains; a quad scene seen over
     n_frames frames of seeded camera drift; trilinear.  Views = frames."""
@@ -107,7 +107,7 @@ def heavy(seed=3, n_tex=256, sides=(512, 1024, 2048, 4096, 8192), q_lo=40, q_hi=
     qs = prm.integers(q_lo, q_hi + 1, n_tex)
     smp = np.where(prm.random(n_tex) < 0.5, 420, 444)
     specs = [(tex_seeds[i], int(side[i]), int(side[i]), int(qs[i]), int(smp[i]), None) for i in range(n_tex)]
-    textures = make_textures(specs, keep_rgb=keep_rgb)
+    textures = make_textures(specs, keep_rgb=keep_rgb, log=log)
     rng = np.random.default_rng(scene_seq)
     sizes = {i: (float(side[i]), float(side[i])) for i in range(n_tex)}
     quads = random_quads(rng, W, H, n_quads, list(range(n_tex)), sizes)
@@ -120,7 +120,7 @@ def heavy(seed=3, n_tex=256, sides=(512, 1024, 2048, 4096, 8192), q_lo=40, q_hi=
 
 def batched(seed=4, n_pool=128, sides=(512, 1024, 2048, 4096), q_lo=50, q_hi=90, n_pairs=2,
             eye=(2064, 2208), n_mono=12, mono_w=(1280, 2560), tex_per_scene=(8, 64), quads_per_mpx=96,
-            filt=FILTER_BILINEAR, name=None) -> Workload:
+            filt=FILTER_BILINEAR, name=None, log=None) -> Workload:
     """Batched recipe: a pool of n_pool 4:2:0 textures (side uniform over
     `sides`, q ~ U{q_lo..q_hi}, full mip chains) seen by n_pairs stereo
     pairs of eye[0] x eye[1] pixels per eye and n_mono mono views of width
@@ -135,7 +135,7 @@ def batched(seed=4, n_pool=128, sides=(512, 1024, 2048, 4096), q_lo=50, q_hi=90,
     side = prm.choice(np.array(sides), n_pool)
     qs = prm.integers(q_lo, q_hi + 1, n_pool)
     specs = [(tex_seeds[i], int(side[i]), int(side[i]), int(qs[i]), 420, None) for i in range(n_pool)]
-    textures = make_textures(specs)
+    textures = make_textures(specs, log=log)
     sizes = {i: (float(side[i]), float(side[i])) for i in range(n_pool)}
     rng = np.random.default_rng(scene_seq)
     from . import similarity
@@ -163,10 +163,10 @@ def batched(seed=4, n_pool=128, sides=(512, 1024, 2048, 4096), q_lo=50, q_hi=90,
                     dict(shapes=shapes, sides=side.tolist(), qualities=qs.tolist()))
 
 
-def batched16() -> Workload:
+def batched16(log=None) -> Workload:
     """The 16-view batch: 2 stereo pairs of 2064x2208 + 12 mono views from
     1280x720 to 2560x1440 over a 128-texture pool of sides 512..4096."""
-    return batched()
+    return batched(log=log)
 
 
 def batched_small(seed=6, filt=FILTER_BILINEAR) -> Workload:
