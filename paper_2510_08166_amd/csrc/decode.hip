@@ -60,16 +60,22 @@ __device__ __noinline__ uint32_t slow_entry(const uint32_t *tab, uint32_t tsel, 
     return JPT_FE_BAD;
 }
 
-// One table lookup of the symbol that starts at the top of `peek` in table
-// t (0 DC luma, 1 AC luma, 3 AC chroma), packed for the chain walk:
-// bits 0-4 bits the symbol takes with its appended bits (0: no valid code),
-// 5-8 run, 9-12 size, 16-31 the coefficient value (or DC difference).
-__device__ __forceinline__ uint32_t decode_at(const uint32_t *tab, uint32_t t, uint32_t thr, uint32_t peek) {
+// The table entry of the symbol that starts at the top of `peek` in table t
+// (0 DC luma, 1 AC luma, 3 AC chroma): the 10-bit fast table, or the direct
+// table of the long codes; entries that neither resolves come from the
+// canonical fallback (never for tables whose long codes fit the direct
+// table, so this stays off the common path).
+__device__ __forceinline__ uint32_t fast_entry(const uint32_t *tab, uint32_t t, uint32_t thr, uint32_t peek) {
     const uint32_t p16 = peek >> 16;
     const uint32_t e1 = tab[t * JPT_FAST_SIZE + (peek >> (32 - JPT_FAST_BITS))];
     const uint32_t e2 = tab[JPT_LONG_OFFSET + t * JPT_LONG_SIZE + min(p16 - thr, (uint32_t)JPT_LONG_SIZE - 1u)];
-    uint32_t e = p16 >= thr ? e2 : e1;
-    if ((e & 31u) == 0 && !(e & JPT_FE_BAD)) e = slow_entry(tab, t, peek);
+    return p16 >= thr ? e2 : e1;
+}
+
+// Packed for the chain walk: bits 0-4 bits the symbol takes with its
+// appended bits (0: no valid code), 5-8 run, 9-12 size, 16-31 the
+// coefficient value (or DC difference).
+__device__ __forceinline__ uint32_t pack_entry(uint32_t e, uint32_t peek) {
     const uint32_t len = e & 31u, size = (e >> 6) & 15u, run = (e >> 10) & 15u;
     const uint32_t fused = (e >> 5) & 1u;
     const uint32_t extra = (uint32_t)(((uint64_t)(peek << len) << size) >> 32);
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(64 * kEntWaves) void k_entropy(const jpt_level_desc
                 cf[(s444 ? 2 : 5) * 64] = (int16_t)dc2;
             }
             const int ndu = s444 ? 3 : 6;
+            const int first_c = s444 ? 1 : 4;  // first chroma data unit
             uint32_t pos = start;
             int du = 0, k = 1, ypred = dc0;
             bool done = false, err = false;
@@ -200,43 +207,43 @@ __global__ __launch_bounds__(64 * kEntWaves) void k_entropy(const jpt_level_desc
                 const uint32_t hi = bit < 32u ? W[0] : (bit < 64u ? W[1] : W[2]);
                 const uint32_t lo = bit < 32u ? W[1] : (bit < 64u ? W[2] : W[3]);
                 const uint32_t peek = (uint32_t)(((((uint64_t)hi) << 32) | lo) << (bit & 31u) >> 32);
-                const uint32_t pA = decode_at(tab, 1, thr[1], peek);
-                const uint32_t pD = decode_at(tab, 0, thr[0], peek);
-                const uint32_t pC = decode_at(tab, 3, thr[3], peek);
+                // one table per step: AC luma or AC chroma for the data unit in
+                // progress; at the start of Y1..Y3 lane 0 looks up the DC
+                // difference instead.  The step ends with the data unit.
+                const uint32_t tac = du >= first_c ? 3u : 1u;
+                const uint32_t tl = (lane == 0 && k == 0) ? 0u : tac;
+                uint32_t e0 = fast_entry(tab, tl, tl == 0 ? thr[0] : thr[tac], peek);
+                if ((e0 & 31u) == 0 && !(e0 & JPT_FE_BAD)) e0 = slow_entry(tab, tl, peek);
+                const uint32_t p0 = pack_entry(e0, peek);
                 // ---- the chain walk (scalar)
                 uint32_t o = 0, wpos = 0xFFFFFFFFu;
                 int wval = 0;
+                if (k == 0) {  // DC difference of Y1..Y3 (lane 0)
+                    const uint32_t e = __builtin_amdgcn_readlane(p0, 0);
+                    ypred += (int)e >> 16;
+                    if ((e & 31u) == 0 || (uint32_t)(ypred + 32768) > 65535u) { err = true; break; }
+                    if (lane == 0) { wpos = (uint32_t)(du * 64); wval = ypred; }
+                    o = e & 31u;
+                    k = 1;
+                }
                 while (o < 64u) {
-                    const bool chroma = s444 ? du != 0 : du >= 4;
-                    const uint32_t e = chroma ? __builtin_amdgcn_readlane(pC, o)
-                                              : (k == 0 ? __builtin_amdgcn_readlane(pD, o)
-                                                        : __builtin_amdgcn_readlane(pA, o));
+                    const uint32_t e = __builtin_amdgcn_readlane(p0, o);
                     const uint32_t used = e & 31u, run = (e >> 5) & 15u, size = (e >> 9) & 15u;
-                    const int value = (int)e >> 16;
-                    if (used == 0) { err = true; break; }
-                    int nk, at = -1, val = 0;
-                    if (k == 0) {  // DC difference of Y1..Y3
-                        ypred += value;
-                        if ((uint32_t)(ypred + 32768) > 65535u) { err = true; break; }
-                        at = 0; val = ypred; nk = 1;
-                    } else if (size != 0) {
-                        at = k + (int)run; val = value; nk = at + 1;
-                        if (at > 63) { err = true; break; }
-                    } else {
-                        nk = run == 15 ? k + 16 : 64;  // ZRL / EOB
-                    }
-                    if (nk > 64) { err = true; break; }
-                    if (at >= 0 && lane == o) {  // the lane that decoded this symbol stores it
+                    const int at = k + (int)run;
+                    const int nk = size != 0 ? at + 1 : (run == 15 ? k + 16 : 64);  // ZRL / EOB
+                    if (used == 0 || nk > 64) { err = true; break; }                 // (at <= 63 when nk <= 64)
+                    if (size != 0 && lane == o) {  // the lane that decoded this coefficient stores it
                         wpos = (uint32_t)(du * 64 + at);
-                        wval = val;
+                        wval = (int)e >> 16;
                     }
                     o += used;
                     k = nk;
-                    if (k == 64) {
-                        du++;
-                        if (du >= ndu) { done = true; break; }
-                        k = (s444 ? du != 0 : du >= 4) ? 1 : 0;
-                    }
+                    if (k == 64) break;
+                }
+                if (k == 64 && !err) {  // end of the data unit
+                    du++;
+                    done = du >= ndu;
+                    k = du >= first_c ? 1 : 0;
                 }
                 if (wpos != 0xFFFFFFFFu) cf[wpos] = (int16_t)wval;
                 pos += o;

@@ -16,9 +16,11 @@ namespace {
 constexpr int kMarkThreads = 256;  // 4 waves per workgroup
 
 __global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint32_t n_words,
-                                               uint32_t *__restrict__ counters) {
+                                               uint32_t *__restrict__ counters, uint64_t *__restrict__ scan,
+                                               uint32_t n_scan) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) vis[w] = 0;
+    for (uint32_t w = i; w < n_scan; w += gridDim.x * blockDim.x) scan[w] = 0;
     if (i < JPT_N_COUNTERS) counters[i] = (i == JPT_CTR_ERROR_ITEM) ? 0xFFFFFFFFu : 0u;
 }
 
@@ -342,6 +344,124 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
     }
 }
 
+// Single-pass compaction for a frame-local cache.  A workgroup draws a
+// ticket (its tile of bitmask words, in the order workgroups start, so all
+// earlier tiles are already running), publishes its tile's packed sum,
+// adds up what earlier tiles published (decoupled look-back: a tile's sum,
+// or its inclusive prefix, which ends the walk) and publishes its own
+// inclusive prefix before listing its items.  status[t]: 0 = nothing yet,
+// else a flag bit and the packed sum (items in bits 0-31, blocks in 32-61).
+constexpr uint64_t kStAgg = 1ull << 62, kStIncl = 1ull << 63, kStSum = kStAgg - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_emit1(const uint32_t *__restrict__ vis,
+                                                        const uint32_t *__restrict__ word_level,
+                                                        const jpt_level_desc *__restrict__ levels, uint32_t n_words,
+                                                        uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
+                                                        uint32_t n_tiles, uint32_t *__restrict__ work,
+                                                        uint32_t max_items, uint32_t *__restrict__ slot_of,
+                                                        uint32_t n_slots, uint32_t *__restrict__ counters) {
+    __shared__ uint32_t s_tile, s_nv[kScanThreads / 64];
+    __shared__ uint64_t s_wave[kScanThreads / 64], s_prefix;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t w0 = tile * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
+    WordCounts wc;
+    uint32_t nv;
+    const uint64_t mine = count_words(vis, nullptr, word_level, levels, n_words, w0, wc, nv);
+    const uint64_t incl = wave_incl_scan(mine, lane);
+    uint32_t nvs = nv;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nvs += __shfl_xor(nvs, d, 64);
+    if (lane == 63) s_wave[wv] = incl;
+    if (lane == 0) s_nv[wv] = nvs;
+    __syncthreads();
+    uint64_t tile_sum = 0, before = 0;
+    uint32_t tile_nv = 0;
+    for (int k = 0; k < kScanThreads / 64; k++) {
+        tile_sum += s_wave[k];
+        tile_nv += s_nv[k];
+        if (k < (int)wv) before += s_wave[k];
+    }
+    if (wv == 0) {
+        uint64_t prefix = 0;
+        if (tile == 0) {
+            if (lane == 0) __hip_atomic_store(status, kStIncl | tile_sum, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(status + tile, kStAgg | tile_sum, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // lanes look at 64 earlier tiles at a time, nearest first
+            int end = (int)tile;
+            bool stuck = false;
+            while (end > 0) {
+                const int p = end - 1 - (int)lane;
+                uint64_t v = kStIncl;  // before tile 0: an inclusive prefix of 0
+                uint32_t spins = 0;
+                while (true) {
+                    if (p >= 0) v = __hip_atomic_load(status + p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (!__ballot(v == 0)) break;
+                    if (++spins > kSpinLimit) { stuck = true; break; }  // cannot happen: bounded anyway
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (stuck) break;
+                const uint64_t im = __ballot((v & kStIncl) != 0);
+                if (im) {
+                    const uint32_t k = (uint32_t)__builtin_ctzll(im);
+                    prefix += wave_sum(lane <= k ? (v & kStSum) : 0ull);
+                    break;
+                }
+                prefix += wave_sum(v & kStSum);
+                end -= 64;
+            }
+            if (lane == 0) {
+                if (stuck) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_INTERNAL);
+                __hip_atomic_store(status + tile, kStIncl | (prefix + tile_sum), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (lane == 0) {
+            s_prefix = prefix;
+            if (tile_nv) atomicAdd(counters + JPT_CTR_VISIBLE, tile_nv);
+        }
+    }
+    __syncthreads();
+    const uint64_t base = s_prefix + before + incl - mine;
+    uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
+    bool overflow = false;
+#pragma unroll
+    for (int i = 0; i < kWpt; i++) {
+        uint32_t m = wc.newm[i];
+        const uint32_t sub = wc.sub[i];
+        while (m) {
+            const uint32_t bit = __builtin_ctz(m);
+            m &= m - 1;
+            const uint32_t b = (w0 + i) * 32 + bit;
+            const bool fits = item + sub <= max_items;
+            for (uint32_t q = 0; q < sub; q++)
+                if (item + q < max_items) work[item + q] = (b << 2) | q;
+            uint32_t slot = JPT_SLOT_NONE;
+            if (blk < n_slots && fits) slot = blk;
+            overflow |= !fits || (slot_of && blk >= n_slots);
+            if (slot_of) slot_of[b] = slot;
+            item += sub;
+            blk += 1;
+        }
+    }
+    if (overflow) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
+    if (tile == n_tiles - 1 && threadIdx.x == kScanThreads - 1) {
+        counters[JPT_CTR_ITEMS] = item < max_items ? item : max_items;
+        counters[JPT_CTR_NEW] = blk;
+    }
+}
+
 // ------------------------------------------------------------ LRU update
 // (paper: "Update Cache", with a slot capacity and oldest-first eviction in
 // place of evicting every block that was not visible.)
@@ -583,7 +703,7 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     uint64_t *scan2 = frame->scan + n_tiles;  // second scan of the frame (LRU ties)
     const uint32_t f = frame->frame_no;
     hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis, n_words,
-                       frame->counters);
+                       frame->counters, frame->scan, lru ? 0u : n_tiles + 2u);
     HIP_CHECK_LAUNCH();
     if (lru) {
         hipLaunchKernelGGL(k_lru_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, cache->tie_mask,
@@ -603,6 +723,15 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         else if (filter == JPT_FILTER_BILINEAR) launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, st);
         else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, st);
         HIP_CHECK_LAUNCH();
+    }
+    if (!lru) {
+        // status words scan[0, n_tiles), ticket in scan[n_tiles] (both cleared above)
+        hipLaunchKernelGGL(k_emit1, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, scene->word_level,
+                           scene->levels, n_words, frame->scan, reinterpret_cast<uint32_t *>(frame->scan + n_tiles),
+                           n_tiles, frame->work, frame->max_items, cache ? cache->slot_of : nullptr,
+                           cache ? cache->n_slots : 0u, frame->counters);
+        HIP_CHECK_LAUNCH();
+        return JPT_OK;
     }
     hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis,
                        lru ? cache->resident : (const uint32_t *)nullptr, scene->word_level, scene->levels, n_words,

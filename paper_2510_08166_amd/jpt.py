@@ -29,7 +29,7 @@ FRAME_AUTO = 0xFFFFFFFF
 TUNE_XCD_TILES = 1
 CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT = range(7)
 N_COUNTERS = 16
-ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL = 1, 2, 4
+ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL, ERR_INTERNAL = 1, 2, 4, 8
 SLOT_NONE = 0xFFFFFFFF
 TEXEL_INVALID = 0xFFFF00FF
 ITEMS_DU = 6
