@@ -78,6 +78,9 @@ typedef int32_t jpt_status;
 
 #define JPT_IDCT_MFMA_F16 0u    /* 64x64 basis on MFMA, split-fp16 operands, fp32 accumulate */
 #define JPT_IDCT_SCALAR_F32 1u  /* separable fp32 row/column IDCT on the vector ALUs */
+#define JPT_IDCT_FUSED_F32 2u   /* jpt_decode_blocks only: the entropy decoder's wavefront runs the
+                                   JPT_IDCT_SCALAR_F32 arithmetic on its own MCU and stores the
+                                   texels; frame->coef is not written */
 
 /* counters[] (u32) of a frame */
 #define JPT_CTR_ITEMS 0         /* work items listed this frame (<= max_items) */

@@ -24,7 +24,7 @@ JPT_OK, JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT, JPT_E_RANGE, JPT_E_BUFSIZE,
     0, -1, -2, -3, -4, -5, -6, -7
 FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR = 0, 1, 2
 CACHE_NONE, CACHE_LRU = 0, 1
-IDCT_MFMA_F16, IDCT_SCALAR_F32 = 0, 1
+IDCT_MFMA_F16, IDCT_SCALAR_F32, IDCT_FUSED_F32 = 0, 1, 2
 FRAME_AUTO = 0xFFFFFFFF
 TUNE_XCD_TILES = 1
 CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT = range(7)

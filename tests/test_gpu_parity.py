@@ -52,6 +52,36 @@ def test_scalar_f32_idct(gpu, case):
     full_parity(wl, idct_mode=jpt.IDCT_SCALAR_F32)
 
 
+@pytest.mark.parametrize("case", ["420 trilinear", "444 ragged", "corrupt"])
+def test_fused_decode_matches_scalar(gpu, case):
+    """JPT_IDCT_FUSED_F32 (entropy decode, IDCT and colour in one kernel) stores
+    exactly the texels of the two-kernel scalar fp32 path."""
+    from paper_2510_08166_amd import jpt
+    if case == "444 ragged":
+        wl = configs.quad_scene(23, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444, filt=configs.FILTER_BILINEAR)
+    else:
+        wl = configs.reduced(seed=13, filt=configs.FILTER_TRILINEAR)
+    kw = {}
+    res = []
+    for mode in (jpt.IDCT_SCALAR_F32, jpt.IDCT_FUSED_F32):
+        import torch
+        r = jpt.Renderer(wl.textures, wl.views, wl.filter)
+        if case == "corrupt":
+            r.scene.streams.fill_(0xFF)
+        r.mark()
+        r.decode(idct_mode=mode)
+        r.resolve()
+        torch.cuda.synchronize()
+        ctr = r.frame.counters_host().copy()
+        n_new = min(int(ctr[jpt.CTR_NEW]), r.cache.n_slots)
+        res.append((ctr, r.frame.work_items(), r.cache.texels[: n_new * 256].cpu().numpy(), r.views.frame_host()))
+    (c0, i0, t0, f0), (c1, i1, t1, f1) = res
+    assert np.array_equal(c0[:7], c1[:7]) and np.array_equal(i0, i1)
+    assert np.array_equal(t0, t1) and np.array_equal(f0, f1)
+    if case == "corrupt":
+        assert c1[jpt.CTR_ERROR] & jpt.ERR_CORRUPT and (f1 == jpt.TEXEL_INVALID).all()
+
+
 def test_many_tiles(gpu):
     # more work items than one decode wave and several scan tiles of bitmask words
     wl = configs.quad_scene(5, 12, 512, 40, 95, 6, 640, 360, 40, filt=configs.FILTER_BILINEAR, name="many tiles")
