@@ -191,13 +191,17 @@ def time_phases(r, steps):
 PHASES = ["mark+compact", "entropy", "idct", "resolve"]
 
 
+IDCT_MODES = {"fused": 2, "mfma": 0, "scalar": 1}
+
+
 def plain_form(args, wl, label, policy=0, n_slots=None):
     """The plain form on one workload: one step = one frame of all its views."""
     import numpy as np
     import torch
     from paper_2510_08166_amd import jpt
     t0 = time.perf_counter()
-    r = jpt.Renderer(wl.textures, wl.views, wl.filter, device="cuda:0", policy=policy, n_slots=n_slots)
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, device="cuda:0", policy=policy, n_slots=n_slots,
+                     idct_mode=IDCT_MODES[args.idct])
     torch.cuda.synchronize()
     log("index built and uploaded in %.1f s" % (time.perf_counter() - t0))
     if policy == jpt.CACHE_LRU:
@@ -214,8 +218,10 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
         raise SystemExit("graph replay disagrees with eager launches")
     eager_ms, med = time_phases(r, args.steps)
     ab = algorithmic_bytes(r, ctr)
-    ab_phase = {"mark+compact": ab["mark"] + ab["compact"], "entropy": ab["entropy"], "idct": ab["idct"],
-                "resolve": ab["resolve"]}
+    fused = r.idct_mode == jpt.IDCT_FUSED_F32
+    ab_phase = {"mark+compact": ab["mark"] + ab["compact"],
+                "entropy": ab["compressed"] + int(ctr[jpt.CTR_NEW]) * 1024 if fused else ab["entropy"],
+                "idct": 0 if fused else ab["idct"], "resolve": ab["resolve"]}
     n_items = int(ctr[jpt.CTR_ITEMS]); n_du = n_items * 6
     dec_ms = float(med[1] + med[2])
     dom = PHASES[int(np.argmax(med))]
@@ -228,7 +234,7 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms/frame", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": label, "views": r.views.n, "pixels": r.views.n_pixels,
+        "config": {"workload": label, "decode": args.idct, "views": r.views.n, "pixels": r.views.n_pixels,
                    "visible_blocks": int(ctr[jpt.CTR_VISIBLE]), "decoded_blocks": int(ctr[jpt.CTR_NEW]),
                    "data_units": n_du},
         "gpu_ms_per_frame_median": round(float(np.median(gpu_frame)), 4),
@@ -416,6 +422,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--idct", default="fused", choices=["fused", "mfma", "scalar"],
+                    help="decode kernels: fused entropy+IDCT+colour, or entropy then the MFMA / scalar IDCT")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is single-GPU (each device would run the same per-frame "

@@ -145,8 +145,10 @@ JPT_DEV int pixel_footprint(const Desc &D, uint32_t n_tex, const jpt_gpixel &px,
     return PIX_VALID;
 }
 
+// Block id of texel (x, y).  Levels are at most 65535 texels on a side, so
+// both factors fit 24 bits and the full-rate 24-bit multiply is exact.
 JPT_DEV uint32_t block_of(const LevelFoot &F, uint32_t x, uint32_t y) {
-    return F.blk_base + (y >> 4) * F.blk_cols + (x >> 4);
+    return F.blk_base + __umul24(y >> 4, F.blk_cols) + (x >> 4);
 }
 
 // ------------------------------------------------------------ view tables

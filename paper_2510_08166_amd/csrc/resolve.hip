@@ -58,7 +58,7 @@ __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const j
                     const int t = 4 * k + 2 * b + a;
                     T.blk[t] = block_of(F, xs[a], ys[b]);
                     T.off[t] = (ys[b] & 15) * 16 + (xs[a] & 15);
-                    T.w[t] = wx[a] * wy[b];
+                    T.w[t] = __umul24(wx[a], wy[b]);  // <= 2^16
                 }
         }
     }
@@ -130,9 +130,10 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
                         const uint32_t w = T.w[t];
                         missing |= (w != 0) && slot[t] == JPT_SLOT_NONE;
                         const uint32_t v = tex[t];
-                        acc[0] += (v & 255) * w;
-                        acc[1] += ((v >> 8) & 255) * w;
-                        acc[2] += ((v >> 16) & 255) * w;
+                        // 8-bit channel x weight <= 2^16: exact in the 24-bit multiply
+                        acc[0] += __umul24(v & 255, w);
+                        acc[1] += __umul24((v >> 8) & 255, w);
+                        acc[2] += __umul24((v >> 16) & 255, w);
                     }
 #pragma unroll
                     for (int c = 0; c < 3; c++) lvl[k][c] = (acc[c] + 32768u) >> 16;
@@ -143,7 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
                     uint32_t a[3] = {lvl[0][0], lvl[0][1], lvl[0][2]};
                     if (kFilter == JPT_FILTER_TRILINEAR && nf == 2) {
 #pragma unroll
-                        for (int c = 0; c < 3; c++) a[c] = (lvl[0][c] * (256 - tw) + lvl[1][c] * tw + 128) >> 8;
+                        for (int c = 0; c < 3; c++)
+                            a[c] = (__umul24(lvl[0][c], 256 - tw) + __umul24(lvl[1][c], tw) + 128) >> 8;
                     }
                     out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
                 }
