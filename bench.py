@@ -314,7 +314,7 @@ def heavy_form(args, reps=None):
     slots = (2 << 30) // 1024
     t0 = time.perf_counter()
     r = jpt.Renderer(wl.textures, [wl.views[0]], wl.filter, device="cuda:0", policy=jpt.CACHE_LRU, n_slots=slots,
-                     max_items=1 << 20)
+                     max_items=1 << 20, idct_mode=IDCT_MODES[args.idct])
     views = [jpt.Views([g]) for g in wl.views]
     torch.cuda.synchronize()
     log("index built and uploaded in %.1f s (%d block ids, %.2f GB compressed)" % (
@@ -353,6 +353,20 @@ def heavy_form(args, reps=None):
     c = r.frame.counters_host()
     if c[jpt.CTR_ERROR]:
         raise SystemExit("device error flags %x after the timed sequences" % c[jpt.CTR_ERROR])
+    # one more sequence, eager, with events between the phases of every frame
+    r.cache.reset(r.scene)
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nf)]
+    for f, v in enumerate(views):
+        r.views = v
+        pev[f][0].record()
+        r.mark()
+        pev[f][1].record()
+        r.decode()
+        pev[f][2].record()
+        r.resolve()
+        pev[f][3].record()
+    torch.cuda.synchronize()
+    phases = np.array([[pev[f][i].elapsed_time(pev[f][i + 1]) for i in range(3)] for f in range(nf)])
     return {"metric": METRIC, "value": round(float(med.mean()), 4), "unit": "ms/frame", "n_gpus": 1,
             "steps": reps * nf, "warmup": 0, "ms_per_step": round(1000.0 * wall / (reps * nf), 4),
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
@@ -361,6 +375,9 @@ def heavy_form(args, reps=None):
                        "pixels_per_frame": int(wl.views[0].size), "block_ids": int(r.scene.n_blocks)},
             "per_frame_ms_median": [round(float(x), 4) for x in med],
             "max_of_medians_ms": round(float(med.max()), 4),
+            "phases_ms_eager": {"mark+compact+lru": [round(float(x), 4) for x in phases[:, 0]],
+                                "decode": [round(float(x), 4) for x in phases[:, 1]],
+                                "resolve": [round(float(x), 4) for x in phases[:, 2]]},
             "frames_visible_new_evicted": counts}
 
 

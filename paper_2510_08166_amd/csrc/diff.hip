@@ -159,42 +159,46 @@ __global__ __launch_bounds__(64) void k_fwd_texels(const jpt_level_desc *__restr
 
 // ------------------------------------------------- float resolve / adjoint
 // Taps of a pixel with their float weights (tap weight x level weight / 2^24).
+// Tap k of a pixel: slot (JPT_SLOT_NONE: block without a slot), texel
+// offset and weight; tap 4j + (2b + a) is texel (x_a, y_b) of level j, and
+// an unused tap has weight 0 (fixed positions keep the arrays in registers).
 struct FTaps {
     uint32_t slot[8], off[8];
     float w[8];
-    int n;
 };
 
 template <class Desc>
 __device__ __forceinline__ int float_taps(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter,
                                           const uint32_t *__restrict__ slot_of, FTaps &T) {
-    T.n = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) { T.slot[k] = 0; T.off[k] = 0; T.w[k] = 0.0f; }
     LevelFoot foot[2];
     int nf;
     uint32_t tw;
     const int st = pixel_footprint(D, n_tex, px, filter, foot, nf, tw);
     if (st != PIX_VALID) return st;
-    for (int k = 0; k < nf; k++) {
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (k >= nf || foot[k].lw == 0) continue;
         const LevelFoot &F = foot[k];
-        if (F.lw == 0) continue;
         if (filter == JPT_FILTER_NEAREST) {
-            const uint32_t b = block_of(F, F.x0, F.y0);
-            T.slot[T.n] = slot_of[b];
-            T.off[T.n] = (F.y0 & 15) * 16 + (F.x0 & 15);
-            T.w[T.n] = (float)(65536u * F.lw) * (1.0f / 16777216.0f);
-            T.n++;
+            T.slot[4 * k] = slot_of[block_of(F, F.x0, F.y0)];
+            T.off[4 * k] = (F.y0 & 15) * 16 + (F.x0 & 15);
+            T.w[4 * k] = (float)(65536u * F.lw) * (1.0f / 16777216.0f);
             continue;
         }
         const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
         const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
+#pragma unroll
         for (int b2 = 0; b2 < 2; b2++)
+#pragma unroll
             for (int a = 0; a < 2; a++) {
+                const int t = 4 * k + 2 * b2 + a;
                 const uint32_t w = wx[a] * wy[b2];
                 if (w == 0) continue;
-                T.slot[T.n] = slot_of[block_of(F, xs[a], ys[b2])];
-                T.off[T.n] = (ys[b2] & 15) * 16 + (xs[a] & 15);
-                T.w[T.n] = (float)(w * F.lw) * (1.0f / 16777216.0f);  // w * lw <= 2^24: exact
-                T.n++;
+                T.slot[t] = slot_of[block_of(F, xs[a], ys[b2])];
+                T.off[t] = (ys[b2] & 15) * 16 + (xs[a] & 15);
+                T.w[t] = (float)(w * F.lw) * (1.0f / 16777216.0f);  // w * lw <= 2^24: exact
             }
     }
     return PIX_VALID;
@@ -223,7 +227,9 @@ __global__ __launch_bounds__(256) void k_fwd_resolve(const jpt_level_desc *__res
     else st = float_taps(GlobalDesc{levels, texs}, n_tex, px, filter, slot_of, T);
     float acc[3] = {0.0f, 0.0f, 0.0f};
     bool bad = st == PIX_INVALID;
-    for (int k = 0; k < T.n; k++) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        if (T.w[k] == 0.0f) continue;
         if (T.slot[k] == JPT_SLOT_NONE) { bad = true; continue; }
         const float *tx = texel_f + (size_t)T.slot[k] * 768 + T.off[k] * 3;
         acc[0] += T.w[k] * tx[0];
@@ -290,8 +296,9 @@ __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__res
         if (st != PIX_VALID) continue;
         const float *g = dframe + ((size_t)y * W + x) * 3;
         const float g0 = g[0], g1 = g[1], g2 = g[2];
-        for (int k = 0; k < T.n; k++) {
-            if (T.slot[k] == JPT_SLOT_NONE) continue;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (T.w[k] == 0.0f || T.slot[k] == JPT_SLOT_NONE) continue;
             acc_add(s_key, s_val, dtexel, T.slot[k] * 256u + T.off[k], __float2ll_rn(g0 * T.w[k] * kFixScale),
                     __float2ll_rn(g1 * T.w[k] * kFixScale), __float2ll_rn(g2 * T.w[k] * kFixScale));
         }

@@ -107,14 +107,26 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
                     if constexpr (kFilter == JPT_FILTER_NEAREST) {
                         ids[0] = block_of(F, F.x0, F.y0);
                     } else {
-                        const bool c0 = F.fx != 256, c1 = F.fx != 0, r0 = F.fy != 256, r1 = F.fy != 0;
-                        if (c0 && r0) ids[4 * k + 0] = block_of(F, F.x0, F.y0);
-                        if (c1 && r0) ids[4 * k + 1] = block_of(F, F.x1, F.y0);
-                        if (c0 && r1) ids[4 * k + 2] = block_of(F, F.x0, F.y1);
-                        if (c1 && r1) ids[4 * k + 3] = block_of(F, F.x1, F.y1);
+                        // the distinct blocks of the texels read with non-zero weight:
+                        // column x1 counts only when x0 is unread or x1 lies in
+                        // the next block column (likewise rows), so no two ids of
+                        // a level are equal
+                        const uint32_t bx0 = F.x0 >> 4, bx1 = F.x1 >> 4, by0 = F.y0 >> 4, by1 = F.y1 >> 4;
+                        const bool c0 = F.fx != 256, c1 = F.fx != 0 && (!c0 || bx1 != bx0);
+                        const bool r0 = F.fy != 256, r1 = F.fy != 0 && (!r0 || by1 != by0);
+                        const uint32_t row0 = F.blk_base + __umul24(by0, F.blk_cols);
+                        const uint32_t row1 = F.blk_base + __umul24(by1, F.blk_cols);
+                        if (c0 && r0) ids[4 * k + 0] = row0 + bx0;
+                        if (c1 && r0) ids[4 * k + 1] = row0 + bx1;
+                        if (c0 && r1) ids[4 * k + 2] = row1 + bx0;
+                        if (c1 && r1) ids[4 * k + 3] = row1 + bx1;
                     }
                 }
             }
+            // drop the ids the left neighbour (the previous pixel of the row)
+            // also holds for the same level slot; ids of different levels
+            // never coincide
+            constexpr int kPerLevel = kFilter == JPT_FILTER_NEAREST ? 1 : 4;
             uint32_t left[kIds];
 #pragma unroll
             for (int k = 0; k < kIds; k++) {
@@ -125,11 +137,9 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
             for (int k = 0; k < kIds; k++) {
                 const uint32_t id = ids[k];
                 bool dup = id == 0xFFFFFFFFu;
+                const int lv0 = (k / kPerLevel) * kPerLevel;
 #pragma unroll
-                for (int j = 0; j < kIds; j++) {
-                    dup |= left[j] == id;
-                    if (j < k) dup |= ids[j] == id;
-                }
+                for (int j = 0; j < kPerLevel; j++) dup |= left[lv0 + j] == id;
                 if (!dup) set_insert(s_key, s_bits, vis, id);
             }
         }
