@@ -23,7 +23,7 @@ enum { PIX_BACKGROUND = 0, PIX_VALID = 1, PIX_INVALID = -1 };
 
 // Non-negative v mod n for sizes that are not powers of two: an out-of-line
 // call, so that the common power-of-two case costs no division code.
-__device__ __noinline__ uint32_t wrap_general(int v, uint32_t n) {
+static __device__ __noinline__ uint32_t wrap_general(int v, uint32_t n) {
     const int r = v % (int)n;
     return (uint32_t)(r < 0 ? r + (int)n : r);
 }

@@ -26,17 +26,17 @@ extern "C" jpt_status jpt_graph_capture(const jpt_scene *scene, const jpt_view *
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (s != JPT_OK || e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s != JPT_OK ? s : JPT_E_HIP;
     }
     jpt_graph *h = new (std::nothrow) jpt_graph;
     if (!h) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return JPT_E_HIP;
     }
     h->graph = g;
     if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         delete h;
         return JPT_E_HIP;
     }
