@@ -237,10 +237,12 @@ typedef struct jpt_view {         /* host struct holding device pointers */
 } jpt_view;
 
 typedef struct jpt_frame {        /* per-frame device scratch, caller-allocated */
-    uint32_t *vis;                /* n_blocks/32 words: blocks this frame reads */
+    uint32_t *vis;                /* n_blocks/32 words: blocks this frame reads; zero-filled by the
+                                     caller before the first frame, every jpt_mark_blocks leaves it so */
     uint32_t *work;               /* max_items work items, ascending */
     uint32_t *counters;           /* JPT_N_COUNTERS */
-    uint64_t *scan;               /* jpt_scan_entries(n_blocks) entries */
+    uint64_t *scan;               /* jpt_scan_entries(n_blocks) entries; zero-filled by the caller
+                                     before the first frame, every jpt_mark_blocks leaves it so */
     int16_t *coef;                /* max_items * 6 * 64 quantised coefficients, zigzag order */
     uint32_t max_items;
     uint32_t frame_no;            /* LRU timestamp f of this frame, or JPT_FRAME_AUTO: the cache's own
@@ -292,8 +294,8 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results nev
  * interleaving neighbouring tiles over all of them. */
 #define JPT_TUNE_XCD_TILES 1u
 
-/* Entries of jpt_frame.scan for a scene of n_blocks block ids (two scans
- * of the block bitmask per frame). */
+/* Entries of jpt_frame.scan for a scene of n_blocks block ids (per-tile
+ * counts of the block bitmask, or two scans of it per LRU frame). */
 uint32_t jpt_scan_entries(uint32_t n_blocks);
 
 /* ------------------------------------------------------------------ *
@@ -301,10 +303,11 @@ uint32_t jpt_scan_entries(uint32_t n_blocks);
  * ------------------------------------------------------------------ */
 
 /* Mark + compact (paper: Mark; decode queue of the overview figure; the
- * cache's visibility flags).  Clears frame->vis and frame->counters, marks
- * every block a pixel of any view reads with non-zero weight under
- * `filter`, then lists the blocks not yet resident as work items in
- * ascending block-id order and assigns their cache slots:
+ * cache's visibility flags).  Marks in frame->vis every block a pixel of
+ * any view reads with non-zero weight under `filter`, then lists the blocks
+ * not yet resident as work items in ascending block-id order, assigns their
+ * cache slots, sets frame->counters for the frame and zeroes frame->vis
+ * again:
  *   JPT_CACHE_NONE: slot = rank of the block among this frame's new blocks
  *     (blocks beyond n_slots get JPT_SLOT_NONE and raise JPT_ERR_CAPACITY);
  *   JPT_CACHE_LRU: the policy stated at jpt_cache (frame_no is the frame

@@ -488,8 +488,10 @@ extern "C" jpt_status jpt_make_level_desc(const jpt_level_info *info, uint64_t s
 }
 
 extern "C" uint32_t jpt_scan_entries(uint32_t n_blocks) {
-    uint32_t words = (n_blocks + 31) / 32;
-    return 2 * ((words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS) + 2;
+    // two scans of an LRU frame, or tile counts + group counts + sync words of a frame-local one
+    const uint32_t words = (n_blocks + 31) / 32;
+    const uint32_t tiles = (words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
+    return 3 * tiles + (tiles + 255) / 256 + 1;
 }
 
 extern "C" uint32_t jpt_version(void) { return JPT_ABI_VERSION; }

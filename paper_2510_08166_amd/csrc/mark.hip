@@ -4,9 +4,11 @@
 // Instead of an atomicCAS into a hash map per pixel, every pixel ORs one bit
 // per footprint block into a dense bitmask (one bit per block id), with the
 // wave first merging equal block ids so that one atomic is issued per
-// distinct block.  A two-kernel scan over the bitmask then lists the new
-// blocks in ascending id order (a deterministic order of the same set the
-// paper queues) and assigns cache slots.
+// distinct block.  The new blocks are then listed in ascending id order (a
+// deterministic order of the same set the paper queues) with their cache
+// slots: without a cache in one pass over the bitmask, from per-tile counts
+// the mark kernel keeps as it sets bits; with the LRU cache by a two-kernel
+// scan.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
@@ -15,12 +17,11 @@ namespace {
 
 constexpr int kMarkThreads = 256;  // 4 waves per workgroup
 
+// (LRU frames) the bitmask and the counters
 __global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint32_t n_words,
-                                               uint32_t *__restrict__ counters, uint64_t *__restrict__ scan,
-                                               uint32_t n_scan) {
+                                               uint32_t *__restrict__ counters) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) vis[w] = 0;
-    for (uint32_t w = i; w < n_scan; w += gridDim.x * blockDim.x) scan[w] = 0;
     if (i < JPT_N_COUNTERS) counters[i] = (i == JPT_CTR_ERROR_ITEM) ? 0xFFFFFFFFu : 0u;
 }
 
@@ -30,8 +31,92 @@ constexpr int kTileW = 64, kTileH = 32;
 // LDS set of the bitmask words touched by the tile (open addressing).
 constexpr int kSetSize = 1024, kSetProbes = 16;
 
+// Per-tile counts of newly set bitmask bits (frame-local cache): tile t =
+// words [256 t, 256 t + 256) in cnt[t], 256 tiles in cnt2[t / 256]; packed
+// as new blocks in the high 32 bits and their work items in the low 32.
+struct TileCounts {
+    uint64_t *cnt, *cnt2;
+    const uint32_t *word_level;
+    const jpt_level_desc *levels;
+};
+
+// vis[word] |= bits; with counts, the bits this call set are added to the
+// word's tile (each bit goes from 0 to 1 once per frame).
+__device__ __forceinline__ void or_bits(uint32_t *__restrict__ vis, uint32_t word, uint32_t bits, const TileCounts &tc) {
+    if (!tc.cnt) {
+        atomicOr(vis + word, bits);
+        return;
+    }
+    const uint32_t old = atomicOr(vis + word, bits);
+    const uint32_t sub = tc.levels[tc.word_level[word]].sampling == JPT_SAMPLING_444 ? 4u : 1u;
+    const uint32_t nb = __popc(bits & ~old);
+    if (nb) {
+        const uint64_t packed = ((uint64_t)nb << 32) | (uint64_t)(nb * sub);
+        atomicAdd((unsigned long long *)(tc.cnt + word / JPT_SCAN_TILE_WORDS), (unsigned long long)packed);
+        atomicAdd((unsigned long long *)(tc.cnt2 + word / (JPT_SCAN_TILE_WORDS * 256u)), (unsigned long long)packed);
+    }
+}
+
+// One HBM atomic per distinct bitmask word of the tile's LDS set, all of a
+// thread's in flight at once.  With counts, the bits they set are summed per
+// scan tile in LDS (s_ctile / s_cval, a few entries: a pixel tile's blocks
+// fall in a few scan tiles) and go out with one atomic per scan tile and
+// group; a scan tile that finds no entry is counted in HBM directly.
+constexpr int kCntSlots = 32;
+
+__device__ __forceinline__ void add_count(uint64_t *__restrict__ cnt, uint64_t *__restrict__ cnt2, uint32_t tile,
+                                          uint64_t packed) {
+    atomicAdd((unsigned long long *)(cnt + tile), (unsigned long long)packed);
+    atomicAdd((unsigned long long *)(cnt2 + tile / 256u), (unsigned long long)packed);
+}
+
+__device__ __forceinline__ void flush_set(const uint32_t *s_key, const uint32_t *s_bits, uint32_t *s_ctile,
+                                          unsigned long long *s_cval, uint32_t *__restrict__ vis,
+                                          const TileCounts &tc) {
+    constexpr int kPer = kSetSize / kMarkThreads;
+    uint32_t key[kPer], bits[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        key[j] = s_key[threadIdx.x + j * kMarkThreads];
+        bits[j] = s_bits[threadIdx.x + j * kMarkThreads];
+    }
+    if (!tc.cnt) {
+#pragma unroll
+        for (int j = 0; j < kPer; j++)
+            if (key[j] != 0xFFFFFFFFu) atomicOr(vis + key[j], bits[j]);
+        return;
+    }
+    uint32_t old[kPer], lv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) old[j] = key[j] != 0xFFFFFFFFu ? atomicOr(vis + key[j], bits[j]) : bits[j];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) lv[j] = key[j] != 0xFFFFFFFFu ? tc.word_level[key[j]] : 0u;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+        const uint32_t nb = __popc(bits[j] & ~old[j]);
+        if (!nb) continue;
+        const uint32_t sub = tc.levels[lv[j]].sampling == JPT_SAMPLING_444 ? 4u : 1u;
+        const uint64_t packed = ((uint64_t)nb << 32) | (uint64_t)(nb * sub);
+        const uint32_t tile = key[j] / JPT_SCAN_TILE_WORDS;
+        uint32_t h = tile & (kCntSlots - 1);
+        bool done = false;
+        for (int p = 0; p < kCntSlots && !done; p++) {
+            const uint32_t o = atomicCAS(s_ctile + h, 0xFFFFFFFFu, tile);
+            if (o == 0xFFFFFFFFu || o == tile) {
+                atomicAdd(s_cval + h, (unsigned long long)packed);
+                done = true;
+            }
+            h = (h + 1) & (kCntSlots - 1);
+        }
+        if (!done) add_count(tc.cnt, tc.cnt2, tile, packed);
+    }
+    __syncthreads();
+    if (threadIdx.x < kCntSlots && s_ctile[threadIdx.x] != 0xFFFFFFFFu)
+        add_count(tc.cnt, tc.cnt2, s_ctile[threadIdx.x], s_cval[threadIdx.x]);
+}
+
 __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, uint32_t *__restrict__ vis,
-                                           uint32_t id) {
+                                           uint32_t id, const TileCounts &tc) {
     const uint32_t word = id >> 5, bit = 1u << (id & 31);
     uint32_t h = (word * 2654435761u) >> (32 - 10);
     for (int p = 0; p < kSetProbes; p++) {
@@ -42,7 +127,7 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
         }
         h = (h + 1) & (kSetSize - 1);
     }
-    atomicOr(vis + word, bit);  // set crowded: go straight to HBM
+    or_bits(vis, word, bit, tc);  // set crowded: go straight to HBM
 }
 
 // One workgroup marks one 64 x 32 pixel tile per step and walks the tiles of
@@ -51,15 +136,17 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
 // G-buffer load in flight.  Each lane drops the block ids that its left
 // neighbour (the previous pixel of the row) also touches, and inserts the
 // rest into the tile's LDS set; the set is flushed to the bitmask with one
-// HBM atomic per distinct word.
+// HBM atomic per distinct word (and, with counts, one per tile level).
 template <uint32_t kFilter, bool kLdsDesc>
 __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                        uint32_t n_lev, const ViewTable tab,
-                                                       uint32_t *__restrict__ vis, uint32_t *__restrict__ counters) {
+                                                       uint32_t *__restrict__ vis, const TileCounts tc,
+                                                       uint32_t *__restrict__ err_word) {
     constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
     constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
-    __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize];
+    __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize], s_ctile[kCntSlots];
+    __shared__ unsigned long long s_cval[kCntSlots];
     __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
     __shared__ uint32_t s_bad;
@@ -82,6 +169,10 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
         for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
             s_key[i] = 0xFFFFFFFFu;
             s_bits[i] = 0;
+        }
+        if (threadIdx.x < kCntSlots) {
+            s_ctile[threadIdx.x] = 0xFFFFFFFFu;
+            s_cval[threadIdx.x] = 0;
         }
         __syncthreads();
 #pragma unroll 1
@@ -140,30 +231,27 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
                 const int lv0 = (k / kPerLevel) * kPerLevel;
 #pragma unroll
                 for (int j = 0; j < kPerLevel; j++) dup |= left[lv0 + j] == id;
-                if (!dup) set_insert(s_key, s_bits, vis, id);
+                if (!dup) set_insert(s_key, s_bits, vis, id, tc);
             }
         }
         __syncthreads();
-        // one HBM atomic per distinct bitmask word of the tile
-        for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
-            const uint32_t k = s_key[i];
-            if (k != 0xFFFFFFFFu) atomicOr(vis + k, s_bits[i]);
-        }
+        flush_set(s_key, s_bits, s_ctile, s_cval, vis, tc);
         __syncthreads();  // the set is reused by the next tile
     }
     if (__ballot(invalid) && lane == 0) atomicOr(&s_bad, 1u);
     __syncthreads();
-    if (threadIdx.x == 0 && s_bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
+    if (threadIdx.x == 0 && s_bad) atomicOr(err_word, JPT_ERR_PIXEL);
 }
 
 template <uint32_t kFilter>
-void launch_mark(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame, hipStream_t st) {
+void launch_mark(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
+                 const TileCounts &tc, uint32_t *err_word, hipStream_t st) {
     if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
         hipLaunchKernelGGL((k_mark<kFilter, true>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, frame->counters);
+                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
     else
         hipLaunchKernelGGL((k_mark<kFilter, false>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, frame->counters);
+                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
 }
 
 // Frame number of an LRU frame: the caller's, or the cache's own counter.
@@ -247,9 +335,10 @@ __device__ __forceinline__ uint64_t count_words(const uint32_t *__restrict__ vis
         const uint32_t w = w0 + i;
         uint32_t v = 0, r = 0, sub = 1;
         if (w < n_words) {
+            const uint32_t lv = word_level[w];  // (loaded beside the bitmask word)
             v = vis[w];
             r = resident ? resident[w] : 0u;
-            if (v & ~r) sub = levels[word_level[w]].sampling == JPT_SAMPLING_444 ? 4u : 1u;
+            if (v & ~r) sub = levels[lv].sampling == JPT_SAMPLING_444 ? 4u : 1u;
         }
         wc.newm[i] = v & ~r;
         wc.sub[i] = sub;
@@ -291,10 +380,10 @@ __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restri
     tile_total(s, tile_sums, counters + JPT_CTR_VISIBLE, nv);
 }
 
-// List the new blocks: work items in ascending block id order and their
-// cache slots (no cache: the block's rank; LRU: popped off the free stack).
-template <bool kLru>
-__global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restrict__ vis,
+// List the new blocks of an LRU frame: work items in ascending block id
+// order and their cache slots, popped off the free stack.  The bitmask words
+// are zeroed behind (the state the frame-local path expects).
+__global__ __launch_bounds__(kScanThreads) void k_emit_lru(uint32_t *__restrict__ vis,
                                                        uint32_t *__restrict__ resident,
                                                        const uint32_t *__restrict__ word_level,
                                                        const jpt_level_desc *__restrict__ levels, uint32_t n_words,
@@ -310,9 +399,12 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
     WordCounts wc;
     uint32_t nv;
     const uint64_t mine = count_words(vis, resident, word_level, levels, n_words, w0, wc, nv);
+#pragma unroll
+    for (int i = 0; i < kWpt; i++)
+        if (w0 + i < n_words) vis[w0 + i] = 0;  // (this thread read it above)
     const uint64_t base = scan_base(tile_sums, mine);
-    const uint32_t top = kLru ? meta[JPT_META_TOP] : 0u;  // free slots after this frame's evictions
-    const uint32_t f = kLru ? lru_frame(frame_no, meta) : 0u;
+    const uint32_t top = meta[JPT_META_TOP];  // free slots after this frame's evictions
+    const uint32_t f = lru_frame(frame_no, meta);
     uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
     bool overflow = false;
 #pragma unroll
@@ -328,23 +420,18 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
             for (uint32_t q = 0; q < sub; q++)
                 if (item + q < max_items) work[item + q] = (b << 2) | q;
             uint32_t slot = JPT_SLOT_NONE;
-            if (kLru) {
-                if (blk < top && fits) {
-                    slot = free_stack[top - 1 - blk];
-                    owner[slot] = b;
-                    last_used[slot] = f;
-                    placed |= 1u << bit;
-                }
-                overflow |= !fits || blk >= top;
-            } else {
-                if (blk < n_slots && fits) slot = blk;
-                overflow |= !fits || (slot_of && blk >= n_slots);
+            if (blk < top && fits) {
+                slot = free_stack[top - 1 - blk];
+                owner[slot] = b;
+                last_used[slot] = f;
+                placed |= 1u << bit;
             }
-            if (slot_of) slot_of[b] = slot;
+            overflow |= !fits || blk >= top;
+            slot_of[b] = slot;
             item += sub;
             blk += 1;
         }
-        if (kLru && placed) resident[w0 + i] |= placed;  // this thread owns the word
+        if (placed) resident[w0 + i] |= placed;  // this thread owns the word
     }
     if (overflow) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
     if (blockIdx.x == n_tiles - 1 && threadIdx.x == kScanThreads - 1) {
@@ -354,98 +441,56 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(const uint32_t *__restric
     }
 }
 
-// Single-pass compaction for a frame-local cache.  A workgroup draws a
-// ticket (its tile of bitmask words, in the order workgroups start, so all
-// earlier tiles are already running), publishes its tile's packed sum,
-// adds up what earlier tiles published (decoupled look-back: a tile's sum,
-// or its inclusive prefix, which ends the walk) and publishes its own
-// inclusive prefix before listing its items.  status[t]: 0 = nothing yet,
-// else a flag bit and the packed sum (items in bits 0-31, blocks in 32-61).
-constexpr uint64_t kStAgg = 1ull << 62, kStIncl = 1ull << 63, kStSum = kStAgg - 1;
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_emit1(const uint32_t *__restrict__ vis,
-                                                        const uint32_t *__restrict__ word_level,
-                                                        const jpt_level_desc *__restrict__ levels, uint32_t n_words,
-                                                        uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
-                                                        uint32_t n_tiles, uint32_t *__restrict__ work,
-                                                        uint32_t max_items, uint32_t *__restrict__ slot_of,
-                                                        uint32_t n_slots, uint32_t *__restrict__ counters) {
-    __shared__ uint32_t s_tile, s_nv[kScanThreads / 64];
-    __shared__ uint64_t s_wave[kScanThreads / 64], s_prefix;
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
+// Compaction for a frame-local cache, one pass over the bitmask.  The mark
+// kernel counted every tile's newly set bits, so a tile's offset is the sum
+// of the counts before it (whole groups of 256 tiles from cnt2, then the
+// tiles of its own group from cnt) and no workgroup waits for another.  Each
+// workgroup lists its tile's work items and slots and zeroes its bitmask
+// words for the next frame; the last one past reading the counts zeroes
+// them and writes the frame's counters.  sync[0]: workgroups past reading;
+// sync[1]: error flags raised by the mark kernel.
+__global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restrict__ vis,
+                                                               const uint32_t *__restrict__ word_level,
+                                                               const jpt_level_desc *__restrict__ levels,
+                                                               uint32_t n_words, uint64_t *__restrict__ cnt,
+                                                               uint64_t *__restrict__ cnt2, uint32_t *__restrict__ sync,
+                                                               uint32_t n_tiles, uint32_t *__restrict__ work,
+                                                               uint32_t max_items, uint32_t *__restrict__ slot_of,
+                                                               uint32_t n_slots, uint32_t *__restrict__ counters) {
+    __shared__ uint64_t s_red[kScanThreads / 64], s_tot[kScanThreads / 64], s_wave[kScanThreads / 64];
+    __shared__ uint32_t s_last;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tile = blockIdx.x;
     const uint32_t w0 = tile * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
+    // offset of the tile (the groups before its group, the tiles before it
+    // in its group) and the frame's total (all groups)
+    const uint32_t grp = tile / 256u, t0 = grp * 256u, n_grp = (n_tiles + 255u) / 256u;
+    const uint64_t g = threadIdx.x < n_grp ? cnt2[threadIdx.x] : 0ull;
+    uint64_t tot = g, pre = threadIdx.x < grp ? g : 0ull;
+    if (t0 + threadIdx.x < tile) pre += cnt[t0 + threadIdx.x];
     WordCounts wc;
     uint32_t nv;
     const uint64_t mine = count_words(vis, nullptr, word_level, levels, n_words, w0, wc, nv);
-    const uint64_t incl = wave_incl_scan(mine, lane);
-    uint32_t nvs = nv;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) nvs += __shfl_xor(nvs, d, 64);
+    for (int i = 0; i < kWpt; i++)
+        if (w0 + i < n_words) vis[w0 + i] = 0;  // (this thread read it above)
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        pre += __shfl_xor(pre, d, 64);
+        tot += __shfl_xor(tot, d, 64);
+    }
+    const uint64_t incl = wave_incl_scan(mine, lane);
+    if (lane == 0) { s_red[wv] = pre; s_tot[wv] = tot; }
     if (lane == 63) s_wave[wv] = incl;
-    if (lane == 0) s_nv[wv] = nvs;
     __syncthreads();
-    uint64_t tile_sum = 0, before = 0;
-    uint32_t tile_nv = 0;
+    // every thread has consumed its count loads: tell the others
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(sync, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == n_tiles - 1;
+    uint64_t base = incl - mine, all = 0;
     for (int k = 0; k < kScanThreads / 64; k++) {
-        tile_sum += s_wave[k];
-        tile_nv += s_nv[k];
-        if (k < (int)wv) before += s_wave[k];
+        base += s_red[k] + (k < (int)wv ? s_wave[k] : 0ull);
+        all += s_tot[k];
     }
-    if (wv == 0) {
-        uint64_t prefix = 0;
-        if (tile == 0) {
-            if (lane == 0) __hip_atomic_store(status, kStIncl | tile_sum, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(status + tile, kStAgg | tile_sum, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            // lanes look at 64 earlier tiles at a time, nearest first
-            int end = (int)tile;
-            bool stuck = false;
-            while (end > 0) {
-                const int p = end - 1 - (int)lane;
-                uint64_t v = kStIncl;  // before tile 0: an inclusive prefix of 0
-                uint32_t spins = 0;
-                while (true) {
-                    if (p >= 0) v = __hip_atomic_load(status + p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    if (!__ballot(v == 0)) break;
-                    if (++spins > kSpinLimit) { stuck = true; break; }  // cannot happen: bounded anyway
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (stuck) break;
-                const uint64_t im = __ballot((v & kStIncl) != 0);
-                if (im) {
-                    const uint32_t k = (uint32_t)__builtin_ctzll(im);
-                    prefix += wave_sum(lane <= k ? (v & kStSum) : 0ull);
-                    break;
-                }
-                prefix += wave_sum(v & kStSum);
-                end -= 64;
-            }
-            if (lane == 0) {
-                if (stuck) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_INTERNAL);
-                __hip_atomic_store(status + tile, kStIncl | (prefix + tile_sum), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (tile_nv) atomicAdd(counters + JPT_CTR_VISIBLE, tile_nv);
-        }
-    }
-    __syncthreads();
-    const uint64_t base = s_prefix + before + incl - mine;
     uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
-    bool overflow = false;
 #pragma unroll
     for (int i = 0; i < kWpt; i++) {
         uint32_t m = wc.newm[i];
@@ -457,18 +502,27 @@ __global__ __launch_bounds__(kScanThreads) void k_emit1(const uint32_t *__restri
             const bool fits = item + sub <= max_items;
             for (uint32_t q = 0; q < sub; q++)
                 if (item + q < max_items) work[item + q] = (b << 2) | q;
-            uint32_t slot = JPT_SLOT_NONE;
-            if (blk < n_slots && fits) slot = blk;
-            overflow |= !fits || (slot_of && blk >= n_slots);
-            if (slot_of) slot_of[b] = slot;
+            if (slot_of) slot_of[b] = blk < n_slots && fits ? blk : JPT_SLOT_NONE;
             item += sub;
             blk += 1;
         }
     }
-    if (overflow) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
-    if (tile == n_tiles - 1 && threadIdx.x == kScanThreads - 1) {
-        counters[JPT_CTR_ITEMS] = item < max_items ? item : max_items;
-        counters[JPT_CTR_NEW] = blk;
+    __syncthreads();
+    if (!s_last) return;
+    // the last workgroup: every other one has read its counts
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kScanThreads) cnt[t] = 0;
+    if (threadIdx.x < n_grp) cnt2[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        const uint32_t items = (uint32_t)all, blocks = (uint32_t)(all >> 32);
+        const bool over = items > max_items || (slot_of && blocks > n_slots);
+        for (uint32_t c = 0; c < JPT_N_COUNTERS; c++) counters[c] = 0;
+        counters[JPT_CTR_ITEMS] = items < max_items ? items : max_items;
+        counters[JPT_CTR_NEW] = blocks;
+        counters[JPT_CTR_VISIBLE] = blocks;
+        counters[JPT_CTR_ERROR] = sync[1] | (over ? JPT_ERR_CAPACITY : 0u);
+        counters[JPT_CTR_ERROR_ITEM] = 0xFFFFFFFFu;
+        sync[0] = 0;
+        sync[1] = 0;
     }
 }
 
@@ -710,12 +764,23 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n_words = scene->n_blocks / 32;
     const uint32_t n_tiles = (n_words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
+    // frame->scan: [0, 2 n_tiles) the two scans of an LRU frame; then, for a
+    // frame-local cache, the tile counts, the group counts and two sync words
     uint64_t *scan2 = frame->scan + n_tiles;  // second scan of the frame (LRU ties)
+    TileCounts tc{nullptr, nullptr, scene->word_level, scene->levels};
+    uint32_t *err_word = frame->counters + JPT_CTR_ERROR;
+    uint32_t *sync = nullptr;
+    if (!lru) {
+        tc.cnt = frame->scan + 2 * (size_t)n_tiles;
+        tc.cnt2 = tc.cnt + n_tiles;
+        sync = reinterpret_cast<uint32_t *>(tc.cnt2 + (n_tiles + 255) / 256);
+        err_word = sync + 1;
+    }
     const uint32_t f = frame->frame_no;
-    hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis, n_words,
-                       frame->counters, frame->scan, lru ? 0u : n_tiles + 2u);
-    HIP_CHECK_LAUNCH();
     if (lru) {
+        hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis, n_words,
+                           frame->counters);
+        HIP_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_lru_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, cache->tie_mask,
                            n_words, cache->meta);
         HIP_CHECK_LAUNCH();
@@ -729,51 +794,41 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         uint32_t groups = tab.span;
         if (tuning && tuning->mark_groups && tuning->mark_groups < groups)
             groups = xcd ? (tuning->mark_groups + 7) / 8 * 8 : tuning->mark_groups;
-        if (filter == JPT_FILTER_NEAREST) launch_mark<JPT_FILTER_NEAREST>(scene, tab, groups, frame, st);
-        else if (filter == JPT_FILTER_BILINEAR) launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, st);
-        else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, st);
+        if (filter == JPT_FILTER_NEAREST) launch_mark<JPT_FILTER_NEAREST>(scene, tab, groups, frame, tc, err_word, st);
+        else if (filter == JPT_FILTER_BILINEAR)
+            launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, tc, err_word, st);
+        else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, tc, err_word, st);
         HIP_CHECK_LAUNCH();
     }
     if (!lru) {
-        // status words scan[0, n_tiles), ticket in scan[n_tiles] (both cleared above)
-        hipLaunchKernelGGL(k_emit1, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, scene->word_level,
-                           scene->levels, n_words, frame->scan, reinterpret_cast<uint32_t *>(frame->scan + n_tiles),
-                           n_tiles, frame->work, frame->max_items, cache ? cache->slot_of : nullptr,
-                           cache ? cache->n_slots : 0u, frame->counters);
+        hipLaunchKernelGGL(k_emit_counted, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, scene->word_level,
+                           scene->levels, n_words, tc.cnt, tc.cnt2, sync, n_tiles, frame->work, frame->max_items,
+                           cache ? cache->slot_of : nullptr, cache ? cache->n_slots : 0u, frame->counters);
         HIP_CHECK_LAUNCH();
         return JPT_OK;
     }
-    hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis,
-                       lru ? cache->resident : (const uint32_t *)nullptr, scene->word_level, scene->levels, n_words,
-                       frame->scan, frame->counters, lru ? cache->slot_of : (const uint32_t *)nullptr,
-                       lru ? cache->last_used : (uint32_t *)nullptr, f, lru ? cache->meta : (const uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
+                       scene->word_level, scene->levels, n_words, frame->scan, frame->counters, cache->slot_of,
+                       cache->last_used, f, cache->meta);
     HIP_CHECK_LAUNCH();
-    if (lru) {
-        const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
-        hipLaunchKernelGGL(k_lru_plan, dim3(1), dim3(256), 0, st, frame->scan, n_tiles, cache->meta);
-        hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                           cache->n_slots, f, cache->meta);
-        hipLaunchKernelGGL(k_lru_threshold, dim3(1), dim3(256), 0, st, cache->meta, frame->counters);
-        hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                           cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
-                           cache->meta);
-        hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
-                           cache->meta);
-        hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
-                           cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
-        HIP_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_emit<true>, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
-                           scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
-                           frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
-                           cache->meta, cache->owner, cache->last_used, f);
-        hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f);
-    } else {
-        hipLaunchKernelGGL(k_emit<false>, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, (uint32_t *)nullptr,
-                           scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
-                           frame->max_items, cache ? cache->slot_of : nullptr, cache ? cache->n_slots : 0u,
-                           frame->counters, (const uint32_t *)nullptr, (const uint32_t *)nullptr,
-                           (uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
-    }
+    const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
+    hipLaunchKernelGGL(k_lru_plan, dim3(1), dim3(256), 0, st, frame->scan, n_tiles, cache->meta);
+    hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                       cache->n_slots, f, cache->meta);
+    hipLaunchKernelGGL(k_lru_threshold, dim3(1), dim3(256), 0, st, cache->meta, frame->counters);
+    hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                       cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
+                       cache->meta);
+    hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                       cache->meta);
+    hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                       cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
+    HIP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_emit_lru, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
+                       scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
+                       frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
+                       cache->meta, cache->owner, cache->last_used, f);
+    hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f);
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }
