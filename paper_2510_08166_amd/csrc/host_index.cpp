@@ -491,7 +491,7 @@ extern "C" uint32_t jpt_scan_entries(uint32_t n_blocks) {
     // two scans of an LRU frame, or tile counts + group counts + sync words of a frame-local one
     const uint32_t words = (n_blocks + 31) / 32;
     const uint32_t tiles = (words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
-    return 3 * tiles + (tiles + 255) / 256 + 1;
+    return 3 * tiles + (tiles + 255) / 256 * 16 + 1;  // 16 count slots per group of 256 tiles
 }
 
 extern "C" uint32_t jpt_version(void) { return JPT_ABI_VERSION; }

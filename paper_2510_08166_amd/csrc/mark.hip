@@ -32,8 +32,11 @@ constexpr int kTileW = 64, kTileH = 32;
 constexpr int kSetSize = 1024, kSetProbes = 16;
 
 // Per-tile counts of newly set bitmask bits (frame-local cache): tile t =
-// words [256 t, 256 t + 256) in cnt[t], 256 tiles in cnt2[t / 256]; packed
+// words [256 t, 256 t + 256) in cnt[t], group g = 256 tiles spread over
+// cnt2[kGrpSlots g, kGrpSlots g + kGrpSlots) (a slot per workgroup modulo
+// kGrpSlots, so that the group's atomics do not all meet at one address); packed
 // as new blocks in the high 32 bits and their work items in the low 32.
+constexpr uint32_t kGrpSlots = 16;
 struct TileCounts {
     uint64_t *cnt, *cnt2;
     const uint32_t *word_level;
@@ -53,7 +56,9 @@ __device__ __forceinline__ void or_bits(uint32_t *__restrict__ vis, uint32_t wor
     if (nb) {
         const uint64_t packed = ((uint64_t)nb << 32) | (uint64_t)(nb * sub);
         atomicAdd((unsigned long long *)(tc.cnt + word / JPT_SCAN_TILE_WORDS), (unsigned long long)packed);
-        atomicAdd((unsigned long long *)(tc.cnt2 + word / (JPT_SCAN_TILE_WORDS * 256u)), (unsigned long long)packed);
+        atomicAdd((unsigned long long *)(tc.cnt2 + word / (JPT_SCAN_TILE_WORDS * 256u) * kGrpSlots +
+                                         blockIdx.x % kGrpSlots),
+                  (unsigned long long)packed);
     }
 }
 
@@ -67,7 +72,8 @@ constexpr int kCntSlots = 32;
 __device__ __forceinline__ void add_count(uint64_t *__restrict__ cnt, uint64_t *__restrict__ cnt2, uint32_t tile,
                                           uint64_t packed) {
     atomicAdd((unsigned long long *)(cnt + tile), (unsigned long long)packed);
-    atomicAdd((unsigned long long *)(cnt2 + tile / 256u), (unsigned long long)packed);
+    atomicAdd((unsigned long long *)(cnt2 + tile / 256u * kGrpSlots + blockIdx.x % kGrpSlots),
+              (unsigned long long)packed);
 }
 
 __device__ __forceinline__ void flush_set(const uint32_t *s_key, const uint32_t *s_bits, uint32_t *s_ctile,
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_lru(uint32_t *__restrict_
 
 // Compaction for a frame-local cache, one pass over the bitmask.  The mark
 // kernel counted every tile's newly set bits, so a tile's offset is the sum
-// of the counts before it (whole groups of 256 tiles from cnt2, then the
+// of the counts before it (whole groups of 256 tiles from the slots of cnt2, then the
 // tiles of its own group from cnt) and no workgroup waits for another.  Each
 // workgroup lists its tile's work items and slots and zeroes its bitmask
 // words for the next frame; the last one past reading the counts zeroes
@@ -464,9 +470,12 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restr
     // offset of the tile (the groups before its group, the tiles before it
     // in its group) and the frame's total (all groups)
     const uint32_t grp = tile / 256u, t0 = grp * 256u, n_grp = (n_tiles + 255u) / 256u;
-    const uint64_t g = threadIdx.x < n_grp ? cnt2[threadIdx.x] : 0ull;
-    uint64_t tot = g, pre = threadIdx.x < grp ? g : 0ull;
-    if (t0 + threadIdx.x < tile) pre += cnt[t0 + threadIdx.x];
+    uint64_t tot = 0, pre = t0 + threadIdx.x < tile ? cnt[t0 + threadIdx.x] : 0ull;
+    for (uint32_t e = threadIdx.x; e < n_grp * kGrpSlots; e += kScanThreads) {
+        const uint64_t g = cnt2[e];
+        tot += g;
+        if (e / kGrpSlots < grp) pre += g;
+    }
     WordCounts wc;
     uint32_t nv;
     const uint64_t mine = count_words(vis, nullptr, word_level, levels, n_words, w0, wc, nv);
@@ -511,7 +520,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restr
     if (!s_last) return;
     // the last workgroup: every other one has read its counts
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kScanThreads) cnt[t] = 0;
-    if (threadIdx.x < n_grp) cnt2[threadIdx.x] = 0;
+    for (uint32_t e = threadIdx.x; e < n_grp * kGrpSlots; e += kScanThreads) cnt2[e] = 0;
     if (threadIdx.x == 0) {
         const uint32_t items = (uint32_t)all, blocks = (uint32_t)(all >> 32);
         const bool over = items > max_items || (slot_of && blocks > n_slots);
@@ -773,7 +782,7 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     if (!lru) {
         tc.cnt = frame->scan + 2 * (size_t)n_tiles;
         tc.cnt2 = tc.cnt + n_tiles;
-        sync = reinterpret_cast<uint32_t *>(tc.cnt2 + (n_tiles + 255) / 256);
+        sync = reinterpret_cast<uint32_t *>(tc.cnt2 + (n_tiles + 255) / 256 * kGrpSlots);
         err_word = sync + 1;
     }
     const uint32_t f = frame->frame_no;
