@@ -34,11 +34,11 @@ JPT_DEV uint32_t wrap(int v, uint32_t n) {
 }
 
 // Texel coordinate along one axis.  Returns false for a non-finite value or
-// |s| >= 2^30.
+// |s| >= 2^30 (the outputs are then meaningless but harmless).
 JPT_DEV bool axis(float u, uint32_t n, bool linear, uint32_t &x0, uint32_t &x1, uint32_t &f) {
     float prod = __fmul_rn(u, (float)n);
     float s = linear ? __fsub_rn(prod, 0.5f) : prod;
-    if (!(fabsf(s) < 1073741824.0f)) return false;
+    const bool ok = fabsf(s) < 1073741824.0f;
     float fl = floorf(s);
     if (linear) {
         float fr = __fsub_rn(s, fl);
@@ -48,9 +48,9 @@ JPT_DEV bool axis(float u, uint32_t n, bool linear, uint32_t &x0, uint32_t &x1, 
     } else {
         f = 0;
     }
-    x0 = wrap((int)fl, n);
+    x0 = wrap(ok ? (int)fl : 0, n);
     x1 = x0 + 1 == n ? 0u : x0 + 1;  // (x + 1) mod n
-    return true;
+    return ok;
 }
 
 // Sampling view of the scene descriptors: texture -> (first level, level
@@ -92,54 +92,60 @@ JPT_DEV void load_desc_lds(const jpt_level_desc *__restrict__ levels, const jpt_
 }
 
 // Levels and footprints of a pixel (up to two levels).  Returns PIX_*.
+// Branch-free over the lanes of a wave: every lane computes with clamped
+// descriptor indices and the checks only pick the status at the end.
 template <class Desc>
 JPT_DEV int pixel_footprint(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter, LevelFoot foot[2],
                             int &nfoot, uint32_t &tw) {
     nfoot = 0;
     tw = 0;
-    if (px.tex == JPT_TEX_BACKGROUND) return PIX_BACKGROUND;
-    if (px.tex >= n_tex) return PIX_INVALID;
-    if (!isfinite(px.u) || !isfinite(px.v) || !isfinite(px.lod)) return PIX_INVALID;
-    const TexRec td = D.tex(px.tex);
+    const bool bg = px.tex == JPT_TEX_BACKGROUND;
+    if (n_tex == 0) return bg ? PIX_BACKGROUND : PIX_INVALID;  // (uniform)
+    bool ok = px.tex < n_tex && isfinite(px.u) && isfinite(px.v) && isfinite(px.lod);
+    const TexRec td = D.tex(px.tex < n_tex ? px.tex : 0u);
     const int L = (int)td.n;
-    if (L <= 0) return PIX_INVALID;
-    int lv[2];
-    uint32_t lw[2];
-    int nl;
+    ok = ok && L > 0;
+    int lv0, nl;
+    uint32_t lw0, lw1 = 0;
     if (filter == JPT_FILTER_TRILINEAR) {
-        float lod = px.lod;
-        if (lod < 0.0f) {
-            lv[0] = 0; nl = 1; lw[0] = 256;
-        } else if (lod >= (float)(L - 1)) {
-            lv[0] = L - 1; nl = 1; lw[0] = 256;
-        } else {
-            float fl = floorf(lod);
-            float fr = __fsub_rn(lod, fl);
-            float sc = __fmul_rn(fr, 256.0f);
-            float t = __fadd_rn(sc, 0.5f);
-            tw = (uint32_t)(int)floorf(t);
-            lv[0] = (int)fl; lv[1] = lv[0] + 1; nl = 2;
-            lw[0] = 256 - tw; lw[1] = tw;
-        }
+        const float lod = px.lod;
+        const float fl = floorf(lod);
+        const float fr = __fsub_rn(lod, fl);
+        const float sc = __fmul_rn(fr, 256.0f);
+        const float t = __fadd_rn(sc, 0.5f);
+        const uint32_t twi = (uint32_t)(int)floorf(t);
+        const bool lo = lod < 0.0f, hi = lod >= (float)(L - 1);
+        const bool two = !lo && !hi;
+        lv0 = lo ? 0 : (hi ? L - 1 : (int)fl);
+        nl = two ? 2 : 1;
+        tw = two ? twi : 0u;
+        lw0 = two ? 256u - twi : 256u;
+        lw1 = twi;
     } else {
-        float t = __fadd_rn(px.lod, 0.5f);
-        int l;
-        if (!(t >= 1.0f)) l = 0;
-        else if (t >= (float)(L - 1)) l = L - 1;
-        else l = (int)floorf(t);
-        lv[0] = l; nl = 1; lw[0] = 256;
+        const float t = __fadd_rn(px.lod, 0.5f);
+        lv0 = !(t >= 1.0f) ? 0 : (t >= (float)(L - 1) ? L - 1 : (int)floorf(t));
+        nl = 1;
+        lw0 = 256;
     }
     const bool linear = filter != JPT_FILTER_NEAREST;
 #pragma unroll
     for (int k = 0; k < 2; k++) {
-        if (k >= nl) break;
+        if (k == 1 && filter != JPT_FILTER_TRILINEAR) break;
         LevelFoot &F = foot[k];
-        const LevRec lr = D.lev(td.first + lv[k]);
+        // (a second level exists only when lv0 + 1 <= L - 1)
+        const uint32_t li = ok ? td.first + (uint32_t)(k == 0 ? lv0 : min(lv0 + 1, L - 1)) : 0u;
+        const LevRec lr = D.lev(li);
         F.blk_base = lr.blk_base;
         F.blk_cols = lr.blk_cols;
-        F.lw = lw[k];
-        if (!axis(px.u, lr.w, linear, F.x0, F.x1, F.fx) || !axis(px.v, lr.h, linear, F.y0, F.y1, F.fy))
-            return PIX_INVALID;
+        F.lw = k == 0 ? lw0 : lw1;
+        const bool ax = axis(px.u, lr.w, linear, F.x0, F.x1, F.fx);
+        const bool ay = axis(px.v, lr.h, linear, F.y0, F.y1, F.fy);
+        if (k < nl) ok = ok && ax && ay;
+    }
+    if (bg) return PIX_BACKGROUND;
+    if (!ok) {
+        tw = 0;
+        return PIX_INVALID;
     }
     nfoot = nl;
     return PIX_VALID;
