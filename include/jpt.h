@@ -95,7 +95,7 @@ typedef int32_t jpt_status;
 #define JPT_ERR_CORRUPT 1u      /* invalid code, > 64 coefficients, or MCU span mismatch */
 #define JPT_ERR_CAPACITY 2u     /* work list or cache slots exhausted */
 #define JPT_ERR_PIXEL 4u        /* G-buffer pixel with bad texture id or coordinates */
-#define JPT_ERR_INTERNAL 8u     /* a bounded device-side wait gave up (results of the frame invalid) */
+#define JPT_ERR_INTERNAL 8u     /* reserved: a bounded device-side wait gave up (no kernel of this version waits) */
 
 #define JPT_SLOT_NONE 0xFFFFFFFFu
 #define JPT_TEX_BACKGROUND 0xFFFFFFFFu
