@@ -286,7 +286,9 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results nev
                                      walks the tiles of all views with that stride) */
     uint32_t resolve_groups;      /* the same for the resolve kernel */
     uint32_t flags;               /* JPT_TUNE_* */
-    uint32_t reserved[3];
+    uint32_t wide_bits;           /* entropy decoder: MCUs of at least this many bits take steps of 128
+                                     bit offsets instead of 64 (0 = auto) */
+    uint32_t reserved[2];
 } jpt_tuning;
 
 /* jpt_tuning.flags: hand each of the GPU's 8 chiplets (XCDs, each with its

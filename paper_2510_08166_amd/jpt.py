@@ -85,7 +85,7 @@ CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1
 
 class TuningC(ctypes.Structure):
     _fields_ = [("decode_groups", u32), ("idct_groups", u32), ("mark_groups", u32), ("resolve_groups", u32),
-                ("flags", u32), ("reserved", u32 * 3)]
+                ("flags", u32), ("wide_bits", u32), ("reserved", u32 * 2)]
 
 
 assert ctypes.sizeof(LevelDesc) == 64 and ctypes.sizeof(TextureDesc) == 16

@@ -27,8 +27,9 @@ CANDIDATES = {
     "resolve_groups": [0, 512, 1024, 2048, 4096],
     "decode_groups": [0, 64, 128, 256, 1024],
     "idct_groups": [0, 128, 256, 512, 1024],
+    "wide_bits": [0, 384, 1024, 1 << 30],
 }
-ORDER = ["flags", "mark_groups", "resolve_groups", "decode_groups", "idct_groups"]
+ORDER = ["flags", "mark_groups", "resolve_groups", "decode_groups", "idct_groups", "wide_bits"]
 
 
 def default_cache_path() -> str:

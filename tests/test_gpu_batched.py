@@ -32,7 +32,8 @@ def test_more_views_than_one_launch_holds(gpu):
 @pytest.mark.parametrize("knobs", [dict(mark_groups=7, resolve_groups=5),
                                    dict(mark_groups=16, resolve_groups=24, flags=1),
                                    dict(flags=1),
-                                   dict(decode_groups=3, idct_groups=2)])
+                                   dict(decode_groups=3, idct_groups=2),
+                                   dict(wide_bits=1), dict(wide_bits=0xFFFFFFFF)])
 def test_launch_knobs_do_not_change_results(gpu, knobs):
     from paper_2510_08166_amd import jpt
     wl = configs.batched_small(seed=8, filt=configs.FILTER_TRILINEAR)

@@ -83,6 +83,27 @@ def test_fused_decode_matches_scalar(gpu, case):
         assert c1[jpt.CTR_ERROR] & jpt.ERR_CORRUPT and (f1[fg] == jpt.TEXEL_INVALID).all()
 
 
+@pytest.mark.parametrize("wide_bits", [1, 0xFFFFFFFF])
+def test_entropy_step_width(gpu, wide_bits):
+    """Every MCU through the decoder's 128-offset steps (wide_bits 1) or
+    none (64-offset steps only): coefficients bit-exact against the oracle
+    for 4:2:0 and ragged 4:4:4, and corrupt streams still flagged."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    t = jpt.TuningC()
+    t.wide_bits = wide_bits
+    wl = configs.reduced(seed=14, filt=configs.FILTER_TRILINEAR)
+    full_parity(wl, tuning=t)
+    full_parity(configs.quad_scene(24, 3, 200, 50, 97, 4, 160, 120, 12, sampling=444,
+                                   filt=configs.FILTER_BILINEAR), tuning=t)
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, tuning=t)
+    r.scene.streams.fill_(0xFF)
+    r.render()
+    torch.cuda.synchronize()
+    assert r.frame.counters_host()[jpt.CTR_ERROR] & jpt.ERR_CORRUPT
+    assert (r.frame.work_items() >> 31).all()
+
+
 def test_many_tiles(gpu):
     # more work items than one decode wave and several scan tiles of bitmask words
     wl = configs.quad_scene(5, 12, 512, 40, 95, 6, 640, 360, 40, filt=configs.FILTER_BILINEAR, name="many tiles")

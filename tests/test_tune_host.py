@@ -5,7 +5,7 @@ from paper_2510_08166_amd import jpt, tune
 
 def test_knobs_round_trip():
     d = {"flags": jpt.TUNE_XCD_TILES, "mark_groups": 1024, "resolve_groups": 0, "decode_groups": 256,
-         "idct_groups": 512}
+         "idct_groups": 512, "wide_bits": 384}
     assert tune.to_dict(tune.from_dict(d)) == d
     assert tune.to_dict(None) == {k: 0 for k in tune.ORDER}
 
