@@ -150,7 +150,8 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
                     out = a[0] | (a[1] << 8) | (a[2] << 16) | 0xFF000000u;
                 }
             }
-            frame[(size_t)y * frame_pitch + x] = out;
+            // (streaming store: nothing in the frame reads the framebuffer back)
+            __builtin_nontemporal_store(out, frame + (size_t)y * frame_pitch + x);
         }
     }
 }
