@@ -81,6 +81,79 @@ def test_graph_replay_matches_eager(gpu):
         assert bad == 0 and parity.frame_diff(f, full) <= 1
 
 
+def _graph_vs_eager(r, n_rep=3):
+    """Replay r's captured frame n_rep times (wiping outputs eagerly between
+    replays) and compare everything it produced with the eager frame."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    r.render()
+    torch.cuda.synchronize()
+    ctr0 = r.frame.counters_host().copy()
+    items0 = r.frame.work_items()
+    n_new = min(int(ctr0[jpt.CTR_NEW]), r.cache.n_slots)
+    tex0 = r.cache.texels[: n_new * 256].cpu().numpy()
+    slots0 = r.cache.slot_of.cpu().numpy()
+    frames0 = [r.views.frame_host(i) for i in range(r.views.n)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = r.capture(s)
+    for rep in range(n_rep):
+        for f in r.views.frames:
+            f.zero_()
+        r.frame.work.zero_()
+        r.frame.counters.zero_()
+        r.cache.texels.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        s.synchronize()
+        ctr = r.frame.counters_host()
+        assert np.array_equal(ctr[:7], ctr0[:7]), "replay %d counters %s vs %s" % (rep, ctr[:7], ctr0[:7])
+        assert np.array_equal(r.frame.work_items(), items0), "replay %d" % rep
+        assert np.array_equal(r.cache.texels[: n_new * 256].cpu().numpy(), tex0), "replay %d" % rep
+        used = items0 & 0x7FFFFFFF
+        assert np.array_equal(r.cache.slot_of.cpu().numpy()[used >> 2], slots0[used >> 2])
+        for i in range(r.views.n):
+            assert np.array_equal(r.views.frame_host(i), frames0[i]), "replay %d view %d" % (rep, i)
+    g.close()
+    return ctr0, frames0
+
+
+@pytest.mark.parametrize("case", ["420 trilinear", "444 bilinear", "corrupt", "capacity", "background"])
+def test_fused_graph_matches_eager(gpu, case):
+    """The captured frame with the fused decode (the benchmark's path)
+    produces exactly the eager frame: work list, counters, slots, texels and
+    framebuffers, also for corrupt streams, exhausted capacity and a
+    background-only frame."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    kw = {}
+    if case == "444 bilinear":
+        wl = configs.quad_scene(25, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444, filt=configs.FILTER_BILINEAR)
+    else:
+        wl = configs.batched_small(seed=11, filt=configs.FILTER_TRILINEAR)
+    if case == "capacity":
+        kw = dict(max_items=100, n_slots=60)
+    if case == "background":
+        for g in wl.views:
+            g["tex"] = 0xFFFFFFFF
+    r = jpt.Renderer(wl.textures, wl.views, wl.filter, idct_mode=jpt.IDCT_FUSED_F32, **kw)
+    if case == "corrupt":
+        r.scene.streams.fill_(0xFF)
+    ctr, frames = _graph_vs_eager(r)
+    if case == "corrupt":
+        assert ctr[jpt.CTR_ERROR] & jpt.ERR_CORRUPT and ctr[jpt.CTR_ERROR_ITEM] == 0
+    elif case == "capacity":
+        assert ctr[jpt.CTR_ERROR] & jpt.ERR_CAPACITY and ctr[jpt.CTR_ITEMS] == 100
+    elif case == "background":
+        assert ctr[jpt.CTR_ITEMS] == 0 and ctr[jpt.CTR_ERROR] == 0
+    else:
+        assert ctr[jpt.CTR_ERROR] == 0
+        osc = oracle.Scene(wl.textures)
+        for gb, f in zip(wl.views, frames):
+            full, _, bad = osc.render(gb, wl.filter)
+            assert bad == 0 and parity.frame_diff(f, full) <= 1
+
+
 def test_lru_graph_counts_frames(gpu):
     """LRU cache inside a replayed graph (frame number kept on the device):
     per frame the same decoded sets, evictions and resident sets as the

@@ -85,10 +85,35 @@ def sampled_pixels(osc, r, frame, gbuf, filt, n, rng, slot_of):
 
 
 def test_frame1080_full_size(gpu):
+    import torch
+    from paper_2510_08166_amd import jpt
     t0 = time.time()
     wl = configs.frame1080()
     log("1080p generated in %.1f s" % (time.time() - t0))
-    full_parity(wl)
+    r, osc, blocks = full_parity(wl)
+    # the benchmark's configuration: fused decode, the frame captured;
+    # bit-exact against the eager fused frame, the same work list as above
+    items = r.frame.work_items()
+    rf = jpt.Renderer(wl.textures, wl.views, wl.filter, idct_mode=jpt.IDCT_FUSED_F32, host=r.host)
+    rf.render()
+    torch.cuda.synchronize()
+    tex0 = rf.cache.texels[: len(blocks) * 256].cpu().numpy()
+    frame0 = rf.views.frame_host(0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = rf.capture(s)
+    rf.cache.texels.zero_()
+    rf.frame.work.zero_()
+    torch.cuda.synchronize()
+    g.launch()
+    s.synchronize()
+    g.close()
+    ctr = rf.frame.counters_host()
+    assert ctr[jpt.CTR_ERROR] == 0 and ctr[jpt.CTR_ITEMS] == len(items)
+    assert np.array_equal(rf.frame.work_items(), items)
+    assert np.array_equal(rf.cache.texels[: len(blocks) * 256].cpu().numpy(), tex0)
+    assert np.array_equal(rf.views.frame_host(0), frame0)
+    log("1080p captured fused frame: bit-exact with the eager frame")
 
 
 def test_batched16_sampled(gpu):
