@@ -18,7 +18,6 @@
 
 namespace {
 
-constexpr int kDu = JPT_ITEMS_DU;
 constexpr int kItemCoefs = JPT_ITEMS_DU * 64;
 // dL/dtexel accumulates in 64-bit fixed point with this many fraction bits,
 // so that the sum does not depend on the order of the atomics
