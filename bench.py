@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # bench reports traffic as null.
 TRAFFIC = {
     # profiles/frame1080_hbm_traffic.txt (k_entropy<true, true>, fused decode, 1080p frame)
-    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "d38ccf7e3e3c1db0",
+    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "8fd589568859308f",
                 "fetch_kib": 553.6, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
