@@ -280,7 +280,7 @@ typedef struct jpt_cache {
 jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, void *stream);
 
 typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results never depend on them. */
-    uint32_t decode_groups;       /* persistent workgroups of the entropy decoder (0 = auto) */
+    uint32_t decode_groups;       /* workgroups of the entropy decoder (0 = as many as the device holds at once) */
     uint32_t idct_groups;         /* persistent workgroups of the IDCT kernel (0 = auto) */
     uint32_t mark_groups;         /* workgroups of the mark kernel (0 = one per pixel tile; else each
                                      walks the tiles of all views with that stride) */

@@ -8,6 +8,10 @@
 #include "jpt.h"
 #include "jpt_internal.h"
 
+// The argument structs keep fixed sizes (bindings mirror them field by field).
+static_assert(sizeof(jpt_level_desc) == 64 && sizeof(jpt_texture_desc) == 16, "descriptor layout");
+static_assert(sizeof(jpt_scene) == 64 && sizeof(jpt_view) == 32 && sizeof(jpt_frame) == 48, "argument layout");
+
 namespace {
 
 // --------------------------------------------------------------- parsing

@@ -25,7 +25,7 @@ CANDIDATES = {
     "flags": [0, jpt.TUNE_XCD_TILES],
     "mark_groups": [0, 512, 1024, 2048, 4096],
     "resolve_groups": [0, 512, 1024, 2048, 4096],
-    "decode_groups": [0, 64, 128, 256, 1024],
+    "decode_groups": [0, 256, 512, 1024],
     "idct_groups": [0, 128, 256, 512, 1024],
     "wide_bits": [0, 384, 1024, 1 << 30],
 }
