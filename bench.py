@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # bench reports traffic as null.
 TRAFFIC = {
     # profiles/frame1080_hbm_traffic.txt (k_entropy<true, true>, fused decode, 1080p frame)
-    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "1859c6033e1e2fd9",
-                "fetch_kib": 1128.4, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "fe1b0d8ddd0df47d",
+                "fetch_kib": 439.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -399,8 +399,15 @@ def batched_extras(args, r, out):
     log("tuned in %.1f s: %s" % (time.perf_counter() - t0, tune.to_dict(knobs)))
     ms_tuned, gpu_tuned = time_graph(r, args.steps, args.warmup)
     ex = {"tuning": tune.to_dict(knobs), "value_default_knobs": out["value"],
+          "value_tuned_knobs": round(ms_tuned, 4),
           "gpu_ms_per_frame_median_tuned": round(float(np.median(gpu_tuned)), 4)}
-    out["value"] = out["ms_per_step"] = round(ms_tuned, 4)
+    # the tuner's short trials can pick knobs that the full timing finds
+    # slower: the line reports the knobs that timed faster here
+    if ms_tuned < out["value"]:
+        out["value"] = out["ms_per_step"] = round(ms_tuned, 4)
+        ex["knobs_used"] = "tuned"
+    else:
+        ex["knobs_used"] = "default"
     # IDCT modes: the MFMA fp16 texels against the scalar fp32 ones
     mode0 = r.idct_mode
     r.idct_mode = jpt.IDCT_MFMA_F16
