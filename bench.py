@@ -138,7 +138,11 @@ def cpu_baseline(wl, budget_s=20.0):
 
 def time_graph(r, steps, warmup):
     """Capture one frame of every view (jpt_graph_capture) on a side stream and
-    time `steps` replays.  Returns (wall ms per frame, per-frame GPU ms)."""
+    time `steps` replays, back to back with nothing between them (wall clock
+    from a synchronised start to a synchronised end); then `steps` more with
+    a timing event after each, for the per-frame GPU times (an event between
+    frames costs about 5 us of its own, so the wall clock comes from the
+    first loop).  Returns (wall ms per frame, per-frame GPU ms)."""
     import numpy as np
     import torch
     side = torch.cuda.Stream()
@@ -148,15 +152,18 @@ def time_graph(r, steps, warmup):
         g.launch()
     side.synchronize()
     with torch.cuda.stream(side):
-        gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(steps):
+            g.launch()
+        side.synchronize()
+        wall = time.perf_counter() - t0
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         gev[0].record(side)
         for s_ in range(steps):
             g.launch()
             gev[s_ + 1].record(side)
         side.synchronize()
-        wall = time.perf_counter() - t0
     g.close()
     gpu = np.array([gev[i].elapsed_time(gev[i + 1]) for i in range(steps)])
     return 1000.0 * wall / steps, gpu

@@ -124,7 +124,9 @@ __device__ __forceinline__ void flush_set(const uint32_t *s_key, const uint32_t 
 __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, uint32_t *__restrict__ vis,
                                            uint32_t id, const TileCounts &tc) {
     const uint32_t word = id >> 5, bit = 1u << (id & 31);
-    uint32_t h = (word * 2654435761u) >> (32 - 10);
+    // slot of a word: its low bits (a tile touches runs of consecutive words,
+    // which this spreads without collisions, at no 32-bit multiply)
+    uint32_t h = word & (kSetSize - 1);
     for (int p = 0; p < kSetProbes; p++) {
         const uint32_t old = atomicCAS(s_key + h, 0xFFFFFFFFu, word);
         if (old == 0xFFFFFFFFu || old == word) {
