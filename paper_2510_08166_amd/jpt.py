@@ -382,6 +382,16 @@ class Views:
     def frame_host(self, i=0) -> np.ndarray:
         return self.frames[i].cpu().numpy().view(np.uint32)
 
+    def view(self, i) -> "Views":
+        """View i alone, sharing its device buffers."""
+        v = Views.__new__(Views)
+        v.gbufs, v.frames = [self.gbufs[i]], [self.frames[i]]
+        v.c = (ViewC * 1)(self.c[i])
+        v.n = 1
+        H, W = self.frames[i].shape
+        v.n_pixels = H * W
+        return v
+
 
 def current_stream():
     return vp(_torch().cuda.current_stream().cuda_stream)
