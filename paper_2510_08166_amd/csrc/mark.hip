@@ -17,12 +17,19 @@ namespace {
 
 constexpr int kMarkThreads = 256;  // 4 waves per workgroup
 
-// (LRU frames) the bitmask and the counters
-__global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint32_t n_words,
-                                               uint32_t *__restrict__ counters) {
+// (LRU frames) the bitmask, the counters, the eviction's tie mask, age
+// histogram and evicted count
+__global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint32_t *__restrict__ tie_mask,
+                                               uint32_t n_words, uint32_t *__restrict__ counters,
+                                               uint32_t *__restrict__ meta, uint32_t n_bins) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) vis[w] = 0;
+    for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) {
+        vis[w] = 0;
+        tie_mask[w] = 0;
+    }
     if (i < JPT_N_COUNTERS) counters[i] = (i == JPT_CTR_ERROR_ITEM) ? 0xFFFFFFFFu : 0u;
+    for (uint32_t k = i; k < n_bins; k += gridDim.x * blockDim.x) meta[JPT_META_HIST + k] = 0;
+    if (i == 0) meta[JPT_META_EVICTED] = 0;
 }
 
 // Pixel tile of one workgroup: 64 x 32 pixels; wave w handles rows
@@ -546,13 +553,6 @@ __device__ __forceinline__ bool bit_set(const uint32_t *__restrict__ mask, uint3
     return (mask[b >> 5] >> (b & 31)) & 1u;
 }
 
-__global__ __launch_bounds__(256) void k_lru_clear(uint32_t *__restrict__ tie_mask, uint32_t n_words,
-                                                   uint32_t *__restrict__ meta) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    for (uint32_t w = i; w < n_words; w += gridDim.x * blockDim.x) tie_mask[w] = 0;
-    for (uint32_t k = i; k < (uint32_t)kAgeBins; k += gridDim.x * blockDim.x) meta[JPT_META_HIST + k] = 0;
-    if (i == 0) meta[JPT_META_EVICTED] = 0;
-}
 
 // Blocks to place and evictions needed.
 __global__ __launch_bounds__(256) void k_lru_plan(const uint64_t *__restrict__ tile_sums, uint32_t n_tiles,
@@ -599,10 +599,16 @@ __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ o
 
 // Oldest bins first: the bin where the evictions end and how many of its
 // blocks go (the smallest block ids).
-__global__ __launch_bounds__(256) void k_lru_threshold(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters) {
+// The eviction threshold of a frame that needs `need` evictions (256
+// threads): the age bin of the last blocks to evict (abin; older bins go
+// whole) and how many of that bin go (ties, the smallest block ids), from
+// the age histogram of the candidates; ties = 0xFFFFFFFF when there are
+// fewer candidates than new blocks (all of them go).  Every thread returns
+// the same values.
+__device__ __forceinline__ void lru_threshold(const uint32_t *__restrict__ meta, uint32_t need, uint32_t &abin,
+                                              uint32_t &ties) {
     __shared__ uint32_t s_sum[256];
-    const uint32_t need = meta[JPT_META_NEED];
-    if (need == 0) return;
+    __shared__ uint32_t s_res[2];
     constexpr int kPer = kAgeBins / 256;
     static_assert(kPer * 256 == kAgeBins, "age bins must split over 256 threads");
     // thread t owns bins [kAgeBins - kPer (t+1), kAgeBins - kPer t): oldest first
@@ -610,6 +616,10 @@ __global__ __launch_bounds__(256) void k_lru_threshold(uint32_t *__restrict__ me
     uint32_t mine = 0;
     for (int k = hi - kPer; k < hi; k++) mine += meta[JPT_META_HIST + k];
     s_sum[threadIdx.x] = mine;
+    if (threadIdx.x == 0) {
+        s_res[0] = 0;
+        s_res[1] = 0xFFFFFFFFu;
+    }
     __syncthreads();
     uint32_t before = 0;  // candidates in older bins
     for (uint32_t t = 0; t < threadIdx.x; t++) before += s_sum[t];
@@ -618,19 +628,16 @@ __global__ __launch_bounds__(256) void k_lru_threshold(uint32_t *__restrict__ me
         for (int k = hi - 1; k >= hi - kPer; k--) {
             const uint32_t h = meta[JPT_META_HIST + k];
             if (c + h >= need) {
-                meta[JPT_META_ABIN] = (uint32_t)k;
-                meta[JPT_META_TIES] = need - c;
+                s_res[0] = (uint32_t)k;
+                s_res[1] = need - c;
                 break;
             }
             c += h;
         }
     }
-    if (threadIdx.x == 255 && before + mine < need) {
-        // fewer candidates than new blocks: evict them all, the rest find no slot
-        meta[JPT_META_ABIN] = 0;
-        meta[JPT_META_TIES] = 0xFFFFFFFFu;
-        atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
-    }
+    __syncthreads();
+    abin = s_res[0];
+    ties = s_res[1];
 }
 
 __device__ __forceinline__ void evict(uint32_t s, uint32_t b, uint32_t *__restrict__ owner,
@@ -644,13 +651,26 @@ __device__ __forceinline__ void evict(uint32_t s, uint32_t b, uint32_t *__restri
 }
 
 // Evict every candidate older than the last bin; mark that bin's blocks.
+// Evict the candidates older than the threshold bin and mark that bin's in
+// the tie mask; every workgroup derives the threshold itself, the first one
+// publishes it for the tie kernels.
 __global__ __launch_bounds__(256) void k_lru_evict(uint32_t *__restrict__ owner, const uint32_t *__restrict__ last_used,
                                                    const uint32_t *__restrict__ vis, uint32_t n_slots,
                                                    uint32_t frame_no, uint32_t *__restrict__ slot_of,
                                                    uint32_t *__restrict__ resident, uint32_t *__restrict__ free_stack,
-                                                   uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta) {
-    if (meta[JPT_META_NEED] == 0) return;
-    const uint32_t abin = meta[JPT_META_ABIN], all = meta[JPT_META_TIES] == 0xFFFFFFFFu;
+                                                   uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta,
+                                                   uint32_t *__restrict__ counters) {
+    const uint32_t need = meta[JPT_META_NEED];
+    if (need == 0) return;
+    uint32_t abin, ties;
+    lru_threshold(meta, need, abin, ties);
+    const bool all = ties == 0xFFFFFFFFu;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        meta[JPT_META_ABIN] = abin;
+        meta[JPT_META_TIES] = ties;
+        // fewer candidates than new blocks: all of them go, the rest find no slot
+        if (all) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
+    }
     const uint32_t f = lru_frame(frame_no, meta);
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
         const uint32_t b = owner[s];
@@ -789,11 +809,8 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     }
     const uint32_t f = frame->frame_no;
     if (lru) {
-        hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis, n_words,
-                           frame->counters);
-        HIP_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_lru_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, cache->tie_mask,
-                           n_words, cache->meta);
+        hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis,
+                           cache->tie_mask, n_words, frame->counters, cache->meta, (uint32_t)kAgeBins);
         HIP_CHECK_LAUNCH();
     }
     const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
@@ -826,10 +843,9 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     hipLaunchKernelGGL(k_lru_plan, dim3(1), dim3(256), 0, st, frame->scan, n_tiles, cache->meta);
     hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->meta);
-    hipLaunchKernelGGL(k_lru_threshold, dim3(1), dim3(256), 0, st, cache->meta, frame->counters);
     hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
-                       cache->meta);
+                       cache->meta, frame->counters);
     hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
                        cache->meta);
     hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
