@@ -312,9 +312,10 @@ __device__ __forceinline__ uint64_t scan_base(const uint64_t *__restrict__ tile_
     return base + incl - mine;
 }
 
-// Sum of one value over the workgroup, written to tile_sums[blockIdx.x].
+// Sum of one value over the workgroup, written to tile_sums[blockIdx.x] and,
+// with grp, added to the tile's group slot (kGrpSlots per 256 tiles).
 __device__ __forceinline__ void tile_total(uint64_t s, uint64_t *__restrict__ tile_sums, uint32_t *vis_counter,
-                                           uint32_t nv) {
+                                           uint32_t nv, uint64_t *__restrict__ grp = nullptr) {
     __shared__ uint64_t s_sum[kScanThreads / 64];
     __shared__ uint32_t s_vis[kScanThreads / 64];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -331,6 +332,9 @@ __device__ __forceinline__ void tile_total(uint64_t s, uint64_t *__restrict__ ti
         for (int k = 0; k < kScanThreads / 64; k++) { t += s_sum[k]; tv += s_vis[k]; }
         tile_sums[blockIdx.x] = t;
         if (vis_counter && tv) atomicAdd(vis_counter, tv);
+        if (grp && t)
+            atomicAdd((unsigned long long *)(grp + blockIdx.x / 256u * kGrpSlots + blockIdx.x % kGrpSlots),
+                      (unsigned long long)t);
     }
 }
 
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restri
                                                         uint32_t *__restrict__ counters,
                                                         const uint32_t *__restrict__ slot_of,
                                                         uint32_t *__restrict__ last_used, uint32_t frame_no,
-                                                        const uint32_t *__restrict__ meta) {
+                                                        const uint32_t *__restrict__ meta, uint64_t *__restrict__ grp) {
     WordCounts wc;
     uint32_t nv;
     const uint32_t w0 = blockIdx.x * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
@@ -392,7 +396,7 @@ __global__ __launch_bounds__(kScanThreads) void k_count(const uint32_t *__restri
             }
         }
     }
-    tile_total(s, tile_sums, counters + JPT_CTR_VISIBLE, nv);
+    tile_total(s, tile_sums, counters + JPT_CTR_VISIBLE, nv, grp);
 }
 
 // List the new blocks of an LRU frame: work items in ascending block id
@@ -554,23 +558,6 @@ __device__ __forceinline__ bool bit_set(const uint32_t *__restrict__ mask, uint3
 }
 
 
-// Blocks to place and evictions needed.
-__global__ __launch_bounds__(256) void k_lru_plan(const uint64_t *__restrict__ tile_sums, uint32_t n_tiles,
-                                                  uint32_t *__restrict__ meta) {
-    __shared__ uint64_t s_part[4];
-    uint64_t s = 0;
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += 256) s += tile_sums[t];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t n_new = (uint32_t)((s_part[0] + s_part[1] + s_part[2] + s_part[3]) >> 32);
-        const uint32_t top = meta[JPT_META_TOP];
-        meta[JPT_META_NEW] = n_new;
-        meta[JPT_META_NEED] = n_new > top ? n_new - top : 0u;
-    }
-}
 
 __device__ __forceinline__ uint32_t age_bin(uint32_t frame_no, uint32_t last) {
     const uint32_t a = frame_no - last;
@@ -578,12 +565,34 @@ __device__ __forceinline__ uint32_t age_bin(uint32_t frame_no, uint32_t last) {
 }
 
 // Histogram of the ages of the eviction candidates (resident, not visible).
+// The frame's plan (new blocks from the group sums of the count kernel;
+// evictions needed = new blocks beyond the free slots), derived by every
+// workgroup and published by the first, then the age histogram of the
+// eviction candidates (resident blocks not visible this frame).
 __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ owner,
                                                   const uint32_t *__restrict__ last_used,
                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
-                                                  uint32_t frame_no, uint32_t *__restrict__ meta) {
+                                                  uint32_t frame_no, uint32_t *__restrict__ meta,
+                                                  const uint64_t *__restrict__ grp, uint32_t n_grp) {
     __shared__ uint32_t s_h[kAgeBins];
-    if (meta[JPT_META_NEED] == 0) return;
+    __shared__ uint32_t s_need;
+    if (threadIdx.x < 64) {
+        uint64_t t = 0;
+        for (uint32_t e = threadIdx.x; e < n_grp; e += 64) t += grp[e];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        if (threadIdx.x == 0) {
+            const uint32_t n_new = (uint32_t)(t >> 32), top = meta[JPT_META_TOP];
+            const uint32_t need = n_new > top ? n_new - top : 0u;
+            s_need = need;
+            if (blockIdx.x == 0) {
+                meta[JPT_META_NEW] = n_new;
+                meta[JPT_META_NEED] = need;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_need == 0) return;
     const uint32_t f = lru_frame(frame_no, meta);
     for (int k = threadIdx.x; k < kAgeBins; k += 256) s_h[k] = 0;
     __syncthreads();
@@ -726,7 +735,8 @@ __global__ __launch_bounds__(kScanThreads) void k_tie_pick(const uint32_t *__res
 
 // Pop the placed blocks off the free stack; report the update.
 __global__ void k_lru_finish(uint32_t *__restrict__ meta, uint32_t *__restrict__ counters, uint32_t n_slots,
-                             uint32_t frame_no) {
+                             uint32_t frame_no, uint64_t *__restrict__ grp, uint32_t n_grp) {
+    for (uint32_t e = threadIdx.x; e < n_grp; e += blockDim.x) grp[e] = 0;  // (zero again for the next frame)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     meta[JPT_META_FRAME] = lru_frame(frame_no, meta) + 1u;
     const uint32_t top = meta[JPT_META_TOP], n_new = meta[JPT_META_NEW];
@@ -796,7 +806,8 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     const uint32_t n_words = scene->n_blocks / 32;
     const uint32_t n_tiles = (n_words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
     // frame->scan: [0, 2 n_tiles) the two scans of an LRU frame; then, for a
-    // frame-local cache, the tile counts, the group counts and two sync words
+    // frame-local cache, the tile counts, the group counts (an LRU frame's
+    // count kernel sums its tiles there) and two sync words
     uint64_t *scan2 = frame->scan + n_tiles;  // second scan of the frame (LRU ties)
     TileCounts tc{nullptr, nullptr, scene->word_level, scene->levels};
     uint32_t *err_word = frame->counters + JPT_CTR_ERROR;
@@ -835,14 +846,17 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
         HIP_CHECK_LAUNCH();
         return JPT_OK;
     }
+    // group sums of the count kernel: the counted compaction's group slots,
+    // unused by an LRU frame (zero between frames)
+    uint64_t *grp = frame->scan + 3 * (size_t)n_tiles;
+    const uint32_t n_grp = (n_tiles + 255) / 256 * kGrpSlots;
     hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
                        scene->word_level, scene->levels, n_words, frame->scan, frame->counters, cache->slot_of,
-                       cache->last_used, f, cache->meta);
+                       cache->last_used, f, cache->meta, grp);
     HIP_CHECK_LAUNCH();
     const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
-    hipLaunchKernelGGL(k_lru_plan, dim3(1), dim3(256), 0, st, frame->scan, n_tiles, cache->meta);
     hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                       cache->n_slots, f, cache->meta);
+                       cache->n_slots, f, cache->meta, grp, n_grp);
     hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
                        cache->meta, frame->counters);
@@ -855,7 +869,8 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
                        scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
                        frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
                        cache->meta, cache->owner, cache->last_used, f);
-    hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f);
+    hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f, grp,
+                       n_grp);
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }
