@@ -296,8 +296,9 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results nev
  * interleaving neighbouring tiles over all of them. */
 #define JPT_TUNE_XCD_TILES 1u
 
-/* Entries of jpt_frame.scan for a scene of n_blocks block ids (per-tile
- * counts of the block bitmask, or two scans of it per LRU frame). */
+/* Entries of jpt_frame.scan for a scene of n_blocks block ids: per-tile
+ * and per-group counts of the block bitmask (an LRU frame also takes two
+ * per-tile scans of it and sums its tiles into the group counts). */
 uint32_t jpt_scan_entries(uint32_t n_blocks);
 
 /* ------------------------------------------------------------------ *
