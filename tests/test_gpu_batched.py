@@ -33,6 +33,7 @@ def test_more_views_than_one_launch_holds(gpu):
                                    dict(mark_groups=16, resolve_groups=24, flags=1),
                                    dict(flags=1),
                                    dict(decode_groups=3, idct_groups=2),
+                                   dict(decode_groups=16, idct_groups=8),
                                    dict(wide_bits=1), dict(wide_bits=0xFFFFFFFF)])
 def test_launch_knobs_do_not_change_results(gpu, knobs):
     from paper_2510_08166_amd import jpt

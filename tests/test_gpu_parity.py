@@ -52,20 +52,25 @@ def test_scalar_f32_idct(gpu, case):
     full_parity(wl, idct_mode=jpt.IDCT_SCALAR_F32)
 
 
-@pytest.mark.parametrize("case", ["420 trilinear", "444 ragged", "corrupt"])
+@pytest.mark.parametrize("case", ["420 trilinear", "444 ragged", "corrupt", "8 decode groups", "16 decode groups"])
 def test_fused_decode_matches_scalar(gpu, case):
     """JPT_IDCT_FUSED_F32 (entropy decode, IDCT and colour in one kernel) stores
-    exactly the texels of the two-kernel scalar fp32 path."""
+    exactly the texels of the two-kernel scalar fp32 path (also on small
+    decode grids, where each wave takes many MCUs and a grid of a multiple of
+    8 workgroups deals them XCD by XCD)."""
     from paper_2510_08166_amd import jpt
     if case == "444 ragged":
         wl = configs.quad_scene(23, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444, filt=configs.FILTER_BILINEAR)
     else:
         wl = configs.reduced(seed=13, filt=configs.FILTER_TRILINEAR)
-    kw = {}
+    tuning = None
+    if case.endswith("decode groups"):
+        tuning = jpt.TuningC()
+        tuning.decode_groups = int(case.split()[0])
     res = []
     for mode in (jpt.IDCT_SCALAR_F32, jpt.IDCT_FUSED_F32):
         import torch
-        r = jpt.Renderer(wl.textures, wl.views, wl.filter)
+        r = jpt.Renderer(wl.textures, wl.views, wl.filter, tuning=tuning if mode == jpt.IDCT_FUSED_F32 else None)
         if case == "corrupt":
             r.scene.streams.fill_(0xFF)
         r.mark()
