@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # bench reports traffic as null.
 TRAFFIC = {
     # profiles/frame1080_hbm_traffic.txt (k_entropy<true, true>, fused decode, 1080p frame)
-    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "fe1b0d8ddd0df47d",
-                "fetch_kib": 439.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "375813762577f7fb",
+                "fetch_kib": 446.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
