@@ -67,6 +67,7 @@ def algorithmic_bytes(r, ctr):
     host = r.host
     # compressed bytes of the decoded MCUs (from the records) + their record share
     comp = 0.0
+    bits = 0
     blocks = (items & 0x7FFFFFFF) >> 2
     lev = host.word_level[blocks >> 5]
     for L in np.unique(lev):
@@ -82,7 +83,9 @@ def algorithmic_bytes(r, ctr):
         sel = blocks[lev == L] - host.blk_base[int(L)]
         bx = sel % inf.blk_cols; by = sel // inf.blk_cols
         mcu = by * inf.mcu_cols + bx
-        comp += float((starts[mcu + 1] - starts[mcu]).sum()) / 8.0 + 64.0 / 9.0 * len(mcu)
+        nb = int((starts[mcu + 1] - starts[mcu]).sum())
+        bits += nb
+        comp += nb / 8.0 + 64.0 / 9.0 * len(mcu)
     nbw = host.n_blocks / 8.0
     return dict(
         mark=P * 16 + nbw,                       # G-buffer read, bitmask set
@@ -92,6 +95,7 @@ def algorithmic_bytes(r, ctr):
         resolve=P * 16 + P * 4 + n_vis * 1024,   # G-buffer, framebuffer, one read of each visible block
         method=P * 16 * 2 + P * 4 + comp + n_new * 1024 + n_vis * 1024 + 2 * nbw,
         compressed=comp,
+        stream_bits=bits,                        # entropy-coded bits of the decoded MCUs
     )
 
 
@@ -284,6 +288,9 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
         "eager_ms_per_frame": round(eager_ms, 4),
         "phases_ms_median": {n: round(float(m), 4) for n, m in zip(PHASES, med)},
         "mblocks_per_s": round(n_du / (dec_ms * 1e-3) / 1e6, 1),
+        # the entropy kernel is bound by its symbol chain, not by bandwidth:
+        # entropy-coded bits of the decoded MCUs per second of the decode phase
+        "entropy_gbit_per_s": round(ab["stream_bits"] / (dec_ms * 1e-3) / 1e9, 1),
         "hbm_gbps_algorithmic": round(ab["method"] / (float(np.median(gpu_frame)) * 1e-3) / 1e9, 1),
         "roofline": roof,
     }
