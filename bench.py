@@ -439,7 +439,8 @@ def batched_extras(args, r, out):
     import torch
     from paper_2510_08166_amd import jpt, tune
     t0 = time.perf_counter()
-    knobs = tune.tune(r, reps=5, cache_path=os.path.join(ROOT, "gpurun_out", "tune.json"), log=log)
+    import tempfile
+    knobs = tune.tune(r, reps=5, cache_path=os.path.join(tempfile.gettempdir(), "jpt_tune.json"), log=log)
     log("tuned in %.1f s: %s" % (time.perf_counter() - t0, tune.to_dict(knobs)))
     ms_tuned, gpu_tuned = time_graph(r, args.steps, args.warmup)
     ex = {"tuning": tune.to_dict(knobs), "value_default_knobs": out["value"],
