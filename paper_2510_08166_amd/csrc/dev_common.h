@@ -77,8 +77,30 @@ struct LdsDesc {
     JPT_DEV LevRec lev(uint32_t i) const { return l[i]; }
 };
 
-// LDS capacity of the descriptor cache of mark and resolve.
+// Texture records in LDS, level records read from HBM (scenes with more
+// levels than the LDS cache holds).
+struct MixDesc {
+    const TexRec *t;
+    const jpt_level_desc *__restrict__ levels;
+    JPT_DEV TexRec tex(uint32_t i) const { return t[i]; }
+    JPT_DEV LevRec lev(uint32_t l) const {
+        const jpt_level_desc *d = levels + l;
+        return LevRec{d->width, d->height, d->blk_base, d->blk_cols};
+    }
+};
+
+// LDS capacity of the descriptor cache of mark and resolve, and the modes:
+// every record in HBM, texture records in LDS, or every record in LDS.
 constexpr uint32_t kLdsTexCap = 512, kLdsLevCap = 1024;
+enum { DESC_HBM = 0, DESC_TEX_LDS = 1, DESC_LDS = 2 };
+inline int desc_mode(uint32_t n_tex, uint32_t n_lev) {
+    return n_tex > kLdsTexCap ? DESC_HBM : (n_lev > kLdsLevCap ? DESC_TEX_LDS : DESC_LDS);
+}
+
+// Copy the texture records into LDS (all threads; the caller synchronises).
+JPT_DEV void load_tex_lds(const jpt_texture_desc *__restrict__ texs, uint32_t n_tex, TexRec *s_t) {
+    for (uint32_t i = threadIdx.x; i < n_tex; i += blockDim.x) s_t[i] = TexRec{texs[i].first_level, texs[i].n_levels};
+}
 
 // Copy the descriptors into LDS (all threads of the block take part; the
 // caller synchronises).

@@ -152,7 +152,7 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
 // neighbour (the previous pixel of the row) also touches, and inserts the
 // rest into the tile's LDS set; the set is flushed to the bitmask with one
 // HBM atomic per distinct word (and, with counts, one per tile level).
-template <uint32_t kFilter, bool kLdsDesc>
+template <uint32_t kFilter, int kDesc>
 __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                        uint32_t n_lev, const ViewTable tab,
@@ -162,12 +162,13 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
     constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize], s_ctile[kCntSlots];
     __shared__ unsigned long long s_cval[kCntSlots];
-    __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
-    __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
+    __shared__ TexRec s_t[kDesc != DESC_HBM ? kLdsTexCap : 1];
+    __shared__ LevRec s_l[kDesc == DESC_LDS ? kLdsLevCap : 1];
     __shared__ uint32_t s_bad;
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_bad = 0;
-    if constexpr (kLdsDesc) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
+    if constexpr (kDesc == DESC_LDS) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
+    if constexpr (kDesc == DESC_TEX_LDS) load_tex_lds(texs, n_tex, s_t);
     bool invalid = false;
     for (uint32_t slot = blockIdx.x; slot < tab.span; slot += gridDim.x) {
         uint32_t view, tx, ty;
@@ -201,7 +202,9 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
             int nf;
             uint32_t tw;
             int st;
-            if constexpr (kLdsDesc) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px, kFilter, foot, nf, tw);
+            if constexpr (kDesc == DESC_LDS) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px, kFilter, foot, nf, tw);
+            else if constexpr (kDesc == DESC_TEX_LDS)
+                st = pixel_footprint(MixDesc{s_t, levels}, n_tex, px, kFilter, foot, nf, tw);
             else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw);
             if (st == PIX_INVALID) {
                 invalid = true;
@@ -258,15 +261,21 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
     if (threadIdx.x == 0 && s_bad) atomicOr(err_word, JPT_ERR_PIXEL);
 }
 
+template <uint32_t kFilter, int kDesc>
+void launch_mark_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
+                      const TileCounts &tc, uint32_t *err_word, hipStream_t st) {
+    hipLaunchKernelGGL((k_mark<kFilter, kDesc>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
+                       scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
+}
+
 template <uint32_t kFilter>
 void launch_mark(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
                  const TileCounts &tc, uint32_t *err_word, hipStream_t st) {
-    if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
-        hipLaunchKernelGGL((k_mark<kFilter, true>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
-    else
-        hipLaunchKernelGGL((k_mark<kFilter, false>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
+    switch (desc_mode(scene->n_textures, scene->n_levels)) {
+    case DESC_LDS: launch_mark_desc<kFilter, DESC_LDS>(scene, tab, groups, frame, tc, err_word, st); break;
+    case DESC_TEX_LDS: launch_mark_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, frame, tc, err_word, st); break;
+    default: launch_mark_desc<kFilter, DESC_HBM>(scene, tab, groups, frame, tc, err_word, st); break;
+    }
 }
 
 // Frame number of an LRU frame: the caller's, or the cache's own counter.

@@ -65,20 +65,19 @@ __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const j
     return PIX_VALID;
 }
 
-template <uint32_t kFilter, bool kLdsDesc>
+template <uint32_t kFilter, int kDesc>
 __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__restrict__ levels,
                                                       const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                       uint32_t n_lev, const ViewTable tab,
                                                       const uint32_t *__restrict__ slot_of,
                                                       const uint32_t *__restrict__ texels) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
-    __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
-    __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
+    __shared__ TexRec s_t[kDesc != DESC_HBM ? kLdsTexCap : 1];
+    __shared__ LevRec s_l[kDesc == DESC_LDS ? kLdsLevCap : 1];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if constexpr (kLdsDesc) {
-        load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
-        __syncthreads();
-    }
+    if constexpr (kDesc == DESC_LDS) load_desc_lds(levels, texs, n_tex, n_lev, s_t, s_l);
+    if constexpr (kDesc == DESC_TEX_LDS) load_tex_lds(texs, n_tex, s_t);
+    if constexpr (kDesc != DESC_HBM) __syncthreads();
     for (uint32_t tslot = blockIdx.x; tslot < tab.span; tslot += gridDim.x) {
         uint32_t view, tx, ty;
         if (!tile_of(tab, tslot, view, tx, ty)) continue;
@@ -101,7 +100,9 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
             Taps<kTaps> T;
             uint32_t tw;
             int nf, st;
-            if constexpr (kLdsDesc) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
+            if constexpr (kDesc == DESC_LDS) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
+            else if constexpr (kDesc == DESC_TEX_LDS)
+                st = pixel_taps<kFilter>(MixDesc{s_t, levels}, n_tex, px[r], T, tw, nf);
             else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
             // all slot lookups of the pixel, then all texel loads
             // unused taps read block 0 / slot 0 (valid addresses) and get weight 0
@@ -156,14 +157,20 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
     }
 }
 
+template <uint32_t kFilter, int kDesc>
+void launch_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache,
+                 hipStream_t st) {
+    hipLaunchKernelGGL((k_resolve<kFilter, kDesc>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
+                       scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
+}
+
 template <uint32_t kFilter>
 void launch(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache, hipStream_t st) {
-    if (scene->n_textures <= kLdsTexCap && scene->n_levels <= kLdsLevCap)
-        hipLaunchKernelGGL((k_resolve<kFilter, true>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
-    else
-        hipLaunchKernelGGL((k_resolve<kFilter, false>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
-                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
+    switch (desc_mode(scene->n_textures, scene->n_levels)) {
+    case DESC_LDS: launch_desc<kFilter, DESC_LDS>(scene, tab, groups, cache, st); break;
+    case DESC_TEX_LDS: launch_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, cache, st); break;
+    default: launch_desc<kFilter, DESC_HBM>(scene, tab, groups, cache, st); break;
+    }
 }
 
 }  // namespace

@@ -34,6 +34,16 @@ def test_reduced_filters(gpu, filt):
     full_parity(wl)
 
 
+@pytest.mark.parametrize("n_tex", [300, 600])
+def test_descriptors_beyond_the_lds_cache(gpu, n_tex):
+    """Scenes with more levels (300 x 5 = 1500) or more textures (600) than the
+    mark and resolve kernels keep in LDS: texture records in LDS and level
+    records from HBM, or every record from HBM."""
+    wl = configs.quad_scene(31, n_tex, 16, 50, 90, 5, 160, 120, 40, filt=configs.FILTER_TRILINEAR,
+                            name="%d textures of 16^2" % n_tex)
+    full_parity(wl)
+
+
 def test_reduced_444_and_ragged(gpu):
     # 4:4:4 textures with a side that is not a multiple of 16 -> partial blocks and MCUs
     wl = configs.quad_scene(21, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444,
