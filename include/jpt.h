@@ -159,8 +159,10 @@ typedef struct jpt_level_info {
  *   stream_out     host, >= info->stream_words u32, or NULL to query
  *   records_out    host, >= info->n_records * 64 bytes, or NULL to query
  * Errors: JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT (any MCU fails to
- * decode), JPT_E_RANGE (an absolute DC outside 12 bits, a relative offset
- * above 65535 bits, stream above 2^32-1 bits), JPT_E_BUFSIZE. */
+ * decode: an invalid code, a (run, size 0) symbol other than EOB and ZRL, an
+ * AC size above 10, a run past coefficient 63), JPT_E_RANGE (a quantised DC
+ * of any data unit outside [-2048, 2047], a relative offset above 65535
+ * bits, stream above 2^32-1 bits), JPT_E_BUFSIZE. */
 jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level_info *info, uint32_t *stream_out,
                            size_t stream_cap_words, uint8_t *records_out, size_t records_cap_bytes);
 
@@ -258,10 +260,14 @@ typedef struct jpt_frame {        /* per-frame device scratch, caller-allocated 
  * first frame.  LRU policy, per frame f with visible set V and resident
  * set R: visible resident blocks get last_used = f; the new blocks V - R
  * take free slots; if too few are free, the resident blocks outside V with
- * the largest age min(f - last_used, JPT_LRU_MAX_AGE) are evicted first,
- * equal ages by the smaller block id. */
+ * the smallest (last_used, block id) are evicted first.  Frame numbers must
+ * not decrease from one frame to the next (ages f - last_used are taken
+ * modulo 2^32).  The eviction ranks ages through a histogram of
+ * JPT_LRU_MAX_AGE + 1 bins; when the evictions end among blocks at least
+ * JPT_LRU_MAX_AGE frames old, three more passes select them by their exact
+ * 32-bit age. */
 #define JPT_LRU_MAX_AGE 1023u
-#define JPT_CACHE_META_WORDS (16u + JPT_LRU_MAX_AGE + 1u)
+#define JPT_CACHE_META_WORDS (16u + JPT_LRU_MAX_AGE + 1u + 2048u + 2048u + 1024u)
 typedef struct jpt_cache {
     uint32_t *texels;             /* n_slots * 256 RGBA8 texels, slot-major, 16x16 row-major */
     uint32_t *slot_of;            /* n_blocks: slot of each block (valid while resident) */
@@ -269,7 +275,7 @@ typedef struct jpt_cache {
     uint32_t *last_used;          /* n_slots: frame_no of last use (LRU) */
     uint32_t *resident;           /* n_blocks/32 words: resident blocks (LRU) */
     uint32_t *free_stack;         /* n_slots: free slots, top of stack in meta (LRU) */
-    uint32_t *meta;               /* JPT_CACHE_META_WORDS: stack top, eviction plan, age histogram (LRU) */
+    uint32_t *meta;               /* JPT_CACHE_META_WORDS: stack top, eviction plan, age histograms (LRU) */
     uint32_t *tie_mask;           /* n_blocks/32 words: scratch of the eviction (LRU) */
     uint32_t n_slots;
     uint32_t policy;              /* JPT_CACHE_NONE / JPT_CACHE_LRU */

@@ -251,18 +251,17 @@ def unpack_frame(frame: np.ndarray) -> np.ndarray:
 
 class LruSim:
     """Frame-granular LRU cache of decoded blocks (the paper's Update Cache
-    pass, with a capacity and oldest-first eviction instead of evicting every
-    invisible block).  Per frame f with visible set V:
+    pass, with a capacity and least-recently-used eviction instead of
+    evicting every invisible block).  Per frame f with visible set V (frame
+    numbers never decrease):
         new   = V - R                      (to decode)
         touch = V & R                      (last_used := f)
         if |new| > free: evict the |new| - free resident blocks not in V with
-        the largest age min(f - last_used, max_age), equal ages by the
-        smaller block id;
+        the smallest (last_used, block id);
         R := (R - evicted) | new,  last_used[new] := f."""
 
-    def __init__(self, capacity: int, max_age: int = 1023):
+    def __init__(self, capacity: int):
         self.capacity = capacity
-        self.max_age = max_age
         self.last_used: dict[int, int] = {}
 
     def step(self, frame_no: int, visible) -> tuple[list, list]:
@@ -274,7 +273,7 @@ class LruSim:
         free = self.capacity - len(R)
         evicted = []
         if len(new) > free:
-            cand = sorted((-min(frame_no - self.last_used[b], self.max_age), b) for b in R - V)
+            cand = sorted((self.last_used[b], b) for b in R - V)
             need = len(new) - free
             if need > len(cand):
                 raise OracleError("visible set exceeds the cache capacity")

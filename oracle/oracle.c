@@ -238,8 +238,10 @@ static int decode_acs(bits_t *b, const huff_t *ac, int16_t zz[64]) {
         int r = rs >> 4, s = rs & 15;
         if (s == 0) {
             if (r == 15) { k += 16; continue; }   /* ZRL: sixteen zeros */
+            if (r != 0) return ORC_E_CORRUPT;      /* (r, 0) is defined only for r = 0 and 15 */
             break;                                 /* EOB */
         }
+        if (s > 10) return ORC_E_CORRUPT;          /* baseline AC magnitudes take at most 10 bits (F.1.2.2) */
         k += r;
         if (k > 63) return ORC_E_CORRUPT;
         zz[k] = (int16_t)extend(receive(b, s), s);

@@ -4,7 +4,8 @@ All inputs are plain numpy arrays read back from the device; nothing here
 calls the GPU library.  The bar:
   - visible blocks, work items, coefficients: bit-exact;
   - texels: within 1 LSB per RGB channel of the fp64 oracle, and every
-    mismatch within 0.01 of a rounding tie of the fp64 value;
+    mismatch within max(1e-3, an a-priori fp32 error bound) of a rounding
+    tie of the fp64 value (texel_tolerance);
   - frames: bit-exact against the oracle's resolve applied to the GPU's own
     texels, within 1 LSB against the oracle's full render.
 """
@@ -102,11 +103,55 @@ def check_coefs(lc: LevelCache, items: np.ndarray, coef_zz: np.ndarray, sample=N
     return bad
 
 
+# Colour-matrix magnitudes per output channel (R, G, B) applied to the
+# errors of the Y, Cb and Cr samples (JFIF full-range inverse).
+_MIX = np.array([[1.0, 0.0, 1.402], [1.0, 0.344136, 0.714136], [1.0, 1.772, 0.0]])
+_U = 2.0 ** -24
+TIE_FLOOR = 1e-3
+
+
+def texel_tolerance(lc: LevelCache, b: int) -> np.ndarray:
+    """[16, 16, 3] distance to a rounding tie within which either neighbour
+    is a correct 8-bit texel: max(1e-3, an a-priori bound on the fp32 error
+    of the GPU paths).  A sample is s = sum F_uv K_uv with |K_uv| <= 1/4;
+    its fp32 evaluation errs by at most 72 u sum|F| / 4 (u = 2^-24: up to 64
+    accumulation roundings, the fp16 hi/lo basis split worth 4 u |K|, the
+    recombination and the basis rounding), and the colour matrix, its fp32
+    constants and the +0.5 of the rounding add at most 4096 u.  sum|F| is
+    taken over the data unit feeding each sample."""
+    L, bx, by = lc.osc.block_coords(b)
+    j = lc.osc.jpegs[L]
+    coef = lc.coef(L)
+    S = np.zeros((16, 16, 3))                     # sum |F| of the Y, Cb, Cr unit of each texel
+    qt = j.quant.astype(np.float64)               # natural order, [luma, chroma]
+
+    def du_sum(m, d, comp):
+        return float(np.abs(coef[m, d].astype(np.float64) * qt[1 if comp else 0]).sum())
+
+    if j.sampling == 420:
+        m = by * j.mcu_cols + bx
+        for ty in range(16):
+            for tx in range(16):
+                S[ty, tx] = (du_sum(m, (ty // 8) * 2 + tx // 8, 0), du_sum(m, 4, 1), du_sum(m, 5, 2))
+    else:
+        for q in range(4):
+            mx, my = 2 * bx + (q & 1), 2 * by + (q >> 1)
+            if mx >= j.mcu_cols or my >= j.mcu_rows:
+                continue
+            m = my * j.mcu_cols + mx
+            S[8 * (q >> 1):8 * (q >> 1) + 8, 8 * (q & 1):8 * (q & 1) + 8] = (du_sum(m, 0, 0), du_sum(m, 1, 1),
+                                                                              du_sum(m, 2, 2))
+    bound = 72.0 * _U * (S @ _MIX.T) / 4.0 + 4096.0 * _U
+    return np.maximum(TIE_FLOOR, bound)
+
+
 def check_texels(lc: LevelCache, blocks: np.ndarray, tiles: np.ndarray, sample=None):
     """tiles: [n_blocks, 256] RGBA8 u32 in slot order (= block order).  Returns
-    (max abs diff, n mismatching channels, max distance of a mismatch to a
-    rounding tie, n channels compared)."""
-    maxd, nmis, tie, n = 0, 0, 0.0, 0
+    (max abs diff, n mismatching channels, worst ratio of a mismatch's
+    distance to a rounding tie over its tolerance (texel_tolerance; <= 1
+    passes, clamped values count as infinitely far), the worst such distance
+    itself, n channels compared)."""
+    maxd, nmis, ratio, dmax, n = 0, 0, 0.0, 0.0, 0
     idx = range(len(blocks)) if sample is None else sample
     for i in idx:
         b = int(blocks[i])
@@ -125,9 +170,11 @@ def check_texels(lc: LevelCache, blocks: np.ndarray, tiles: np.ndarray, sample=N
             fv = f[:h, :w][mis]
             clamped = (fv > 255.49) | (fv < -0.49)
             dist = np.abs(np.abs(fv - np.floor(fv)) - 0.5)
-            dist[clamped] = 1.0
-            tie = max(tie, float(dist.max()))
-    return maxd, nmis, tie, n
+            dist[clamped] = np.inf
+            tol = texel_tolerance(lc, b)[:h, :w][mis]
+            ratio = max(ratio, float((dist / tol).max()))
+            dmax = max(dmax, float(dist.max()))
+    return maxd, nmis, ratio, dmax, n
 
 
 def levels_from_tiles(osc: Scene, blocks: np.ndarray, tiles: np.ndarray) -> dict:

@@ -289,15 +289,19 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
             br.pos += s;
             pred[c] += extend_bits(raw, s);
             if (pred[c] < -32768 || pred[c] > 32767) return JPT_E_CORRUPT;
+            // every quantised DC of an 8-bit baseline image fits 12 bits; the
+            // records store the absolute ones in 12 bits, and the decoders'
+            // arithmetic assumes it of the differential ones too
+            if (pred[c] < -2048 || pred[c] > 2047) return JPT_E_RANGE;
             if (absolute) {
-                if (pred[c] < -2048 || pred[c] > 2047) return JPT_E_RANGE;
                 dcs[(size_t)m * 3 + c] = pred[c];
                 // splice: copy the pending original bits, skip this DC code
                 copy_bits(ww, P.ecs.data(), ecs_bits, copied_from, dc_from - copied_from);
                 removed += br.pos - dc_from;
                 copied_from = br.pos;
             }
-            for (int k = 1; k < 64;) {
+            int k = 1;
+            while (k < 64) {
                 int rs = decode_symbol(acC[tsel], br.peek32(), &len);
                 if (rs < 0) return JPT_E_CORRUPT;
                 br.pos += len;
@@ -313,6 +317,7 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
                 br.pos += sz;
                 k++;
             }
+            if (k > 64) return JPT_E_CORRUPT;  // a run of zeros (ZRL) past the last position
             if (br.overrun()) return JPT_E_CORRUPT;
         }
     }

@@ -37,12 +37,23 @@
 // JPT_STREAM_PAD_WORDS zero words, rounded up to whole 16-byte vectors.
 #define JPT_STREAM_WORDS(bits) (((((uint64_t)(bits) + 31) / 32 + JPT_STREAM_PAD_WORDS) + 3) & ~(uint64_t)3)
 
-// LRU cache metadata (jpt_cache.meta): scalars, then the age histogram.
+// LRU cache metadata (jpt_cache.meta): scalars, then the age histogram of
+// the eviction candidates (ages capped at JPT_LRU_MAX_AGE), then the three
+// digit histograms of the exact selection inside the capped bin (digit 0 =
+// age >> 21, digit 1 = (age >> 10) & 2047, digit 2 = age & 1023).
 #define JPT_META_TOP 0        // free slots on the stack
 #define JPT_META_NEW 1        // blocks to place this frame
 #define JPT_META_NEED 2       // evictions needed this frame
 #define JPT_META_ABIN 3       // age bin of the last evicted blocks
-#define JPT_META_TIES 4       // blocks of that bin to evict (smallest ids)
+#define JPT_META_TIES 4       // blocks of equal age to evict (smallest ids)
 #define JPT_META_EVICTED 5    // evicted this frame
 #define JPT_META_FRAME 6      // frame number of the next frame (JPT_FRAME_AUTO)
+#define JPT_META_DEEP 7       // 1: the evictions end inside the capped bin
+#define JPT_META_D0 8         // chosen digit 0, and evictions left below it
+#define JPT_META_R0 9
+#define JPT_META_D1 10        // chosen digit 1, and evictions left below it
+#define JPT_META_R1 11
 #define JPT_META_HIST 16      // JPT_LRU_MAX_AGE + 1 bins
+#define JPT_META_DH0 (JPT_META_HIST + JPT_LRU_MAX_AGE + 1)  // 2048 bins
+#define JPT_META_DH1 (JPT_META_DH0 + 2048)                  // 2048 bins
+#define JPT_META_DH2 (JPT_META_DH1 + 2048)                  // 1024 bins

@@ -18,7 +18,7 @@ namespace {
 constexpr int kMarkThreads = 256;  // 4 waves per workgroup
 
 // (LRU frames) the bitmask, the counters, the eviction's tie mask, age
-// histogram and evicted count
+// histograms, evicted count and deep-selection flag
 __global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint32_t *__restrict__ tie_mask,
                                                uint32_t n_words, uint32_t *__restrict__ counters,
                                                uint32_t *__restrict__ meta, uint32_t n_bins) {
@@ -29,7 +29,10 @@ __global__ __launch_bounds__(256) void k_clear(uint32_t *__restrict__ vis, uint3
     }
     if (i < JPT_N_COUNTERS) counters[i] = (i == JPT_CTR_ERROR_ITEM) ? 0xFFFFFFFFu : 0u;
     for (uint32_t k = i; k < n_bins; k += gridDim.x * blockDim.x) meta[JPT_META_HIST + k] = 0;
-    if (i == 0) meta[JPT_META_EVICTED] = 0;
+    if (i == 0) {
+        meta[JPT_META_EVICTED] = 0;
+        meta[JPT_META_DEEP] = 0;
+    }
 }
 
 // Pixel tile of one workgroup: 64 x 32 pixels; wave w handles rows
@@ -558,32 +561,46 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restr
 }
 
 // ------------------------------------------------------------ LRU update
-// (paper: "Update Cache", with a slot capacity and oldest-first eviction in
-// place of evicting every block that was not visible.)
+// (paper: "Update Cache", with a slot capacity and least-recently-used
+// eviction in place of evicting every block that was not visible.)  The
+// candidates (resident, not visible) are ranked by age f - last_used, the
+// oldest going first and equal ages by the smaller block id.  A histogram of
+// ages capped at JPT_LRU_MAX_AGE finds the age where the evictions end; when
+// that is the capped bin, three radix passes over the candidates' exact
+// 32-bit ages (digits of 11, 11 and 10 bits) narrow it to one age.
 constexpr int kAgeBins = JPT_LRU_MAX_AGE + 1;
+constexpr uint32_t kCap = JPT_LRU_MAX_AGE;
+constexpr int kDigitBins = 2048;
 
 __device__ __forceinline__ bool bit_set(const uint32_t *__restrict__ mask, uint32_t b) {
     return (mask[b >> 5] >> (b & 31)) & 1u;
 }
 
+__device__ __forceinline__ uint32_t age_of(uint32_t frame_no, uint32_t last) { return frame_no - last; }
+__device__ __forceinline__ uint32_t age_bin(uint32_t age) { return age < kCap ? age : kCap; }
+__device__ __forceinline__ uint32_t digit0(uint32_t age) { return age >> 21; }
+__device__ __forceinline__ uint32_t digit1(uint32_t age) { return (age >> 10) & 2047u; }
+__device__ __forceinline__ uint32_t digit2(uint32_t age) { return age & 1023u; }
 
-
-__device__ __forceinline__ uint32_t age_bin(uint32_t frame_no, uint32_t last) {
-    const uint32_t a = frame_no - last;
-    return a < (uint32_t)JPT_LRU_MAX_AGE ? a : (uint32_t)JPT_LRU_MAX_AGE;
+// Add an LDS histogram to one in HBM (non-zero bins only).
+template <int kBins>
+__device__ __forceinline__ void flush_hist(const uint32_t *s_h, uint32_t *__restrict__ g) {
+    for (int k = threadIdx.x; k < kBins; k += 256)
+        if (s_h[k]) atomicAdd(g + k, s_h[k]);
 }
 
-// Histogram of the ages of the eviction candidates (resident, not visible).
 // The frame's plan (new blocks from the group sums of the count kernel;
 // evictions needed = new blocks beyond the free slots), derived by every
-// workgroup and published by the first, then the age histogram of the
-// eviction candidates (resident blocks not visible this frame).
+// workgroup and published by the first, then the histogram of the
+// candidates' capped ages and, for the candidates in the capped bin, of
+// their first age digit.
 __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ owner,
                                                   const uint32_t *__restrict__ last_used,
                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
                                                   uint32_t frame_no, uint32_t *__restrict__ meta,
                                                   const uint64_t *__restrict__ grp, uint32_t n_grp) {
     __shared__ uint32_t s_h[kAgeBins];
+    __shared__ uint32_t s_d[kDigitBins];
     __shared__ uint32_t s_need;
     if (threadIdx.x < 64) {
         uint64_t t = 0;
@@ -604,35 +621,36 @@ __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ o
     if (s_need == 0) return;
     const uint32_t f = lru_frame(frame_no, meta);
     for (int k = threadIdx.x; k < kAgeBins; k += 256) s_h[k] = 0;
+    for (int k = threadIdx.x; k < kDigitBins; k += 256) s_d[k] = 0;
     __syncthreads();
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
         const uint32_t b = owner[s];
         if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
-        atomicAdd(s_h + age_bin(f, last_used[s]), 1u);
+        const uint32_t age = age_of(f, last_used[s]);
+        atomicAdd(s_h + age_bin(age), 1u);
+        if (age >= kCap) atomicAdd(s_d + digit0(age), 1u);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kAgeBins; k += 256)
-        if (s_h[k]) atomicAdd(meta + JPT_META_HIST + k, s_h[k]);
+    flush_hist<kAgeBins>(s_h, meta + JPT_META_HIST);
+    flush_hist<kDigitBins>(s_d, meta + JPT_META_DH0);
 }
 
-// Oldest bins first: the bin where the evictions end and how many of its
-// blocks go (the smallest block ids).
-// The eviction threshold of a frame that needs `need` evictions (256
-// threads): the age bin of the last blocks to evict (abin; older bins go
-// whole) and how many of that bin go (ties, the smallest block ids), from
-// the age histogram of the candidates; ties = 0xFFFFFFFF when there are
-// fewer candidates than new blocks (all of them go).  Every thread returns
-// the same values.
-__device__ __forceinline__ void lru_threshold(const uint32_t *__restrict__ meta, uint32_t need, uint32_t &abin,
-                                              uint32_t &ties) {
+// Where `need` evictions end in a histogram taken oldest (highest bin)
+// first: the bin of the last evicted candidates (higher bins go whole) and
+// how many of that bin go; rest = 0xFFFFFFFF when the histogram holds fewer
+// than `need` candidates (all of them go).  256 threads; every thread
+// returns the same values.
+template <int kBins>
+__device__ __forceinline__ void select_bin(const uint32_t *__restrict__ hist, uint32_t need, uint32_t &bin,
+                                           uint32_t &rest) {
     __shared__ uint32_t s_sum[256];
     __shared__ uint32_t s_res[2];
-    constexpr int kPer = kAgeBins / 256;
-    static_assert(kPer * 256 == kAgeBins, "age bins must split over 256 threads");
-    // thread t owns bins [kAgeBins - kPer (t+1), kAgeBins - kPer t): oldest first
-    const int hi = kAgeBins - kPer * (int)threadIdx.x;
+    constexpr int kPer = kBins / 256;
+    static_assert(kPer * 256 == kBins, "bins must split over 256 threads");
+    // thread t owns bins [kBins - kPer (t+1), kBins - kPer t): oldest first
+    const int hi = kBins - kPer * (int)threadIdx.x;
     uint32_t mine = 0;
-    for (int k = hi - kPer; k < hi; k++) mine += meta[JPT_META_HIST + k];
+    for (int k = hi - kPer; k < hi; k++) mine += hist[k];
     s_sum[threadIdx.x] = mine;
     if (threadIdx.x == 0) {
         s_res[0] = 0;
@@ -644,7 +662,7 @@ __device__ __forceinline__ void lru_threshold(const uint32_t *__restrict__ meta,
     if (before < need && before + mine >= need) {
         uint32_t c = before;
         for (int k = hi - 1; k >= hi - kPer; k--) {
-            const uint32_t h = meta[JPT_META_HIST + k];
+            const uint32_t h = hist[k];
             if (c + h >= need) {
                 s_res[0] = (uint32_t)k;
                 s_res[1] = need - c;
@@ -654,8 +672,8 @@ __device__ __forceinline__ void lru_threshold(const uint32_t *__restrict__ meta,
         }
     }
     __syncthreads();
-    abin = s_res[0];
-    ties = s_res[1];
+    bin = s_res[0];
+    rest = s_res[1];
 }
 
 __device__ __forceinline__ void evict(uint32_t s, uint32_t b, uint32_t *__restrict__ owner,
@@ -668,34 +686,116 @@ __device__ __forceinline__ void evict(uint32_t s, uint32_t b, uint32_t *__restri
     atomicAdd(meta + JPT_META_EVICTED, 1u);
 }
 
-// Evict every candidate older than the last bin; mark that bin's blocks.
 // Evict the candidates older than the threshold bin and mark that bin's in
 // the tie mask; every workgroup derives the threshold itself, the first one
-// publishes it for the tie kernels.
+// publishes it for the tie kernels.  When the threshold is the capped bin,
+// this is the first pass of the exact selection instead: the candidates of
+// that bin whose first age digit is above the chosen one go, and the second
+// digits of those at the chosen one are counted.
 __global__ __launch_bounds__(256) void k_lru_evict(uint32_t *__restrict__ owner, const uint32_t *__restrict__ last_used,
                                                    const uint32_t *__restrict__ vis, uint32_t n_slots,
                                                    uint32_t frame_no, uint32_t *__restrict__ slot_of,
                                                    uint32_t *__restrict__ resident, uint32_t *__restrict__ free_stack,
                                                    uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta,
                                                    uint32_t *__restrict__ counters) {
+    __shared__ uint32_t s_d[kDigitBins];
     const uint32_t need = meta[JPT_META_NEED];
     if (need == 0) return;
     uint32_t abin, ties;
-    lru_threshold(meta, need, abin, ties);
+    select_bin<kAgeBins>(meta + JPT_META_HIST, need, abin, ties);
     const bool all = ties == 0xFFFFFFFFu;
+    const bool deep = !all && abin == kCap;
+    uint32_t d0 = 0, r0 = 0;
+    if (deep) select_bin<kDigitBins>(meta + JPT_META_DH0, ties, d0, r0);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         meta[JPT_META_ABIN] = abin;
         meta[JPT_META_TIES] = ties;
+        meta[JPT_META_DEEP] = deep ? 1u : 0u;
+        meta[JPT_META_D0] = d0;
+        meta[JPT_META_R0] = r0;
         // fewer candidates than new blocks: all of them go, the rest find no slot
         if (all) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
+    }
+    if (deep) {
+        for (int k = threadIdx.x; k < kDigitBins; k += 256) s_d[k] = 0;
+        __syncthreads();
     }
     const uint32_t f = lru_frame(frame_no, meta);
     for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
         const uint32_t b = owner[s];
         if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
-        const uint32_t bin = age_bin(f, last_used[s]);
-        if (bin > abin || all) evict(s, b, owner, slot_of, resident, free_stack, meta);
-        else if (bin == abin) atomicOr(tie_mask + (b >> 5), 1u << (b & 31));
+        const uint32_t age = age_of(f, last_used[s]);
+        const uint32_t bin = age_bin(age);
+        if (all || bin > abin) {
+            evict(s, b, owner, slot_of, resident, free_stack, meta);
+        } else if (bin == abin) {
+            if (!deep) atomicOr(tie_mask + (b >> 5), 1u << (b & 31));
+            else if (digit0(age) > d0) evict(s, b, owner, slot_of, resident, free_stack, meta);
+            else if (digit0(age) == d0) atomicAdd(s_d + digit1(age), 1u);
+        }
+    }
+    if (deep) {
+        __syncthreads();
+        flush_hist<kDigitBins>(s_d, meta + JPT_META_DH1);
+    }
+}
+
+// Second pass of the exact selection: inside the chosen first digit, the
+// candidates whose second digit is above the chosen one go, and the third
+// digits of those at the chosen one are counted.
+__global__ __launch_bounds__(256) void k_lru_deep1(uint32_t *__restrict__ owner,
+                                                   const uint32_t *__restrict__ last_used,
+                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
+                                                   uint32_t frame_no, uint32_t *__restrict__ slot_of,
+                                                   uint32_t *__restrict__ resident,
+                                                   uint32_t *__restrict__ free_stack, uint32_t *__restrict__ meta) {
+    __shared__ uint32_t s_d[1024];
+    if (meta[JPT_META_DEEP] == 0) return;
+    const uint32_t d0 = meta[JPT_META_D0];
+    uint32_t d1, r1;
+    select_bin<kDigitBins>(meta + JPT_META_DH1, meta[JPT_META_R0], d1, r1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        meta[JPT_META_D1] = d1;
+        meta[JPT_META_R1] = r1;
+    }
+    for (int k = threadIdx.x; k < 1024; k += 256) s_d[k] = 0;
+    __syncthreads();
+    const uint32_t f = lru_frame(frame_no, meta);
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
+        const uint32_t b = owner[s];
+        if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
+        const uint32_t age = age_of(f, last_used[s]);
+        if (age < kCap || digit0(age) != d0) continue;
+        if (digit1(age) > d1) evict(s, b, owner, slot_of, resident, free_stack, meta);
+        else if (digit1(age) == d1) atomicAdd(s_d + digit2(age), 1u);
+    }
+    __syncthreads();
+    flush_hist<1024>(s_d, meta + JPT_META_DH2);
+}
+
+// Last pass: the candidates of the chosen first two digits whose third digit
+// is above the chosen one go; those of exactly the chosen age are marked in
+// the tie mask, of which the tie kernels evict the smallest ids.
+__global__ __launch_bounds__(256) void k_lru_deep2(uint32_t *__restrict__ owner,
+                                                   const uint32_t *__restrict__ last_used,
+                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
+                                                   uint32_t frame_no, uint32_t *__restrict__ slot_of,
+                                                   uint32_t *__restrict__ resident,
+                                                   uint32_t *__restrict__ free_stack,
+                                                   uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta) {
+    if (meta[JPT_META_DEEP] == 0) return;
+    const uint32_t d0 = meta[JPT_META_D0], d1 = meta[JPT_META_D1];
+    uint32_t d2, r2;
+    select_bin<1024>(meta + JPT_META_DH2, meta[JPT_META_R1], d2, r2);
+    if (blockIdx.x == 0 && threadIdx.x == 0) meta[JPT_META_TIES] = r2;
+    const uint32_t f = lru_frame(frame_no, meta);
+    for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
+        const uint32_t b = owner[s];
+        if (b == JPT_SLOT_NONE || bit_set(vis, b)) continue;
+        const uint32_t age = age_of(f, last_used[s]);
+        if (age < kCap || digit0(age) != d0 || digit1(age) != d1) continue;
+        if (digit2(age) > d2) evict(s, b, owner, slot_of, resident, free_stack, meta);
+        else if (digit2(age) == d2) atomicOr(tie_mask + (b >> 5), 1u << (b & 31));
     }
 }
 
@@ -798,14 +898,37 @@ extern "C" jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, 
     return JPT_OK;
 }
 
-extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
-                                      jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
+namespace {
+
+// Argument checks shared by both mark entry points (all but the scan buffer).
+jpt_status mark_args(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                     const jpt_frame *frame) {
     if (!scene || !frame || (n_views && !views)) return JPT_E_ARG;
     if (filter > JPT_FILTER_TRILINEAR) return JPT_E_ARG;
     if (!scene->levels || !scene->textures || !scene->word_level || scene->n_blocks == 0 ||
         (scene->n_blocks & 31) || scene->n_blocks > (1u << 29))
         return JPT_E_ARG;
-    if (!frame->vis || !frame->work || !frame->counters || !frame->scan) return JPT_E_ARG;
+    if (!frame->vis || !frame->work || !frame->counters) return JPT_E_ARG;
+    return JPT_OK;
+}
+
+jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                      jpt_frame *frame, uint64_t *scan, jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+}  // namespace
+
+extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                                      jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
+    const jpt_status s = mark_args(scene, views, n_views, filter, frame);
+    if (s != JPT_OK) return s;
+    if (!frame->scan) return JPT_E_ARG;
+    return mark_frame(scene, views, n_views, filter, frame, frame->scan, cache, tuning, stream);
+}
+
+namespace {
+
+jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                      jpt_frame *frame, uint64_t *scan, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
     const bool lru = cache && cache->policy == JPT_CACHE_LRU;
     if (cache && cache->policy > JPT_CACHE_LRU) return JPT_E_ARG;
     if (lru && !lru_ok(cache)) return JPT_E_ARG;
@@ -814,15 +937,15 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     hipStream_t st = (hipStream_t)stream;
     const uint32_t n_words = scene->n_blocks / 32;
     const uint32_t n_tiles = (n_words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
-    // frame->scan: [0, 2 n_tiles) the two scans of an LRU frame; then, for a
+    // scan: [0, 2 n_tiles) the two scans of an LRU frame; then, for a
     // frame-local cache, the tile counts, the group counts (an LRU frame's
     // count kernel sums its tiles there) and two sync words
-    uint64_t *scan2 = frame->scan + n_tiles;  // second scan of the frame (LRU ties)
+    uint64_t *scan2 = scan + n_tiles;  // second scan of the frame (LRU ties)
     TileCounts tc{nullptr, nullptr, scene->word_level, scene->levels};
     uint32_t *err_word = frame->counters + JPT_CTR_ERROR;
     uint32_t *sync = nullptr;
     if (!lru) {
-        tc.cnt = frame->scan + 2 * (size_t)n_tiles;
+        tc.cnt = scan + 2 * (size_t)n_tiles;
         tc.cnt2 = tc.cnt + n_tiles;
         sync = reinterpret_cast<uint32_t *>(tc.cnt2 + (n_tiles + 255) / 256 * kGrpSlots);
         err_word = sync + 1;
@@ -830,7 +953,8 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     const uint32_t f = frame->frame_no;
     if (lru) {
         hipLaunchKernelGGL(k_clear, dim3(grid_for(n_words, 256, 1024)), dim3(256), 0, st, frame->vis,
-                           cache->tie_mask, n_words, frame->counters, cache->meta, (uint32_t)kAgeBins);
+                           cache->tie_mask, n_words, frame->counters, cache->meta,
+                           (uint32_t)(JPT_CACHE_META_WORDS - JPT_META_HIST));
         HIP_CHECK_LAUNCH();
     }
     const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
@@ -857,10 +981,10 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     }
     // group sums of the count kernel: the counted compaction's group slots,
     // unused by an LRU frame (zero between frames)
-    uint64_t *grp = frame->scan + 3 * (size_t)n_tiles;
+    uint64_t *grp = scan + 3 * (size_t)n_tiles;
     const uint32_t n_grp = (n_tiles + 255) / 256 * kGrpSlots;
     hipLaunchKernelGGL(k_count, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
-                       scene->word_level, scene->levels, n_words, frame->scan, frame->counters, cache->slot_of,
+                       scene->word_level, scene->levels, n_words, scan, frame->counters, cache->slot_of,
                        cache->last_used, f, cache->meta, grp);
     HIP_CHECK_LAUNCH();
     const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
@@ -869,13 +993,19 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
                        cache->meta, frame->counters);
+    const uint32_t dg = grid_for(cache->n_slots, 256, 512);
+    hipLaunchKernelGGL(k_lru_deep1, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                       cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
+    hipLaunchKernelGGL(k_lru_deep2, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                       cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
+                       cache->meta);
     hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
                        cache->meta);
     hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
                        cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
     HIP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_emit_lru, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
-                       scene->word_level, scene->levels, n_words, frame->scan, n_tiles, frame->work,
+                       scene->word_level, scene->levels, n_words, scan, n_tiles, frame->work,
                        frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
                        cache->meta, cache->owner, cache->last_used, f);
     hipLaunchKernelGGL(k_lru_finish, dim3(1), dim3(64), 0, st, cache->meta, frame->counters, cache->n_slots, f, grp,
@@ -883,3 +1013,5 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     HIP_CHECK_LAUNCH();
     return JPT_OK;
 }
+
+}  // namespace

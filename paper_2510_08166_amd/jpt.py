@@ -80,7 +80,7 @@ class CacheC(ctypes.Structure):
 
 
 LRU_MAX_AGE = 1023
-CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1
+CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1 + 2048 + 2048 + 1024
 
 
 class TuningC(ctypes.Structure):

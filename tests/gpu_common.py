@@ -35,10 +35,12 @@ def full_parity(wl, coef_sample=None, texel_sample=None, full_render=True, idct_
     assert ctr[jpt.CTR_NEW] == len(blocks) and ctr[jpt.CTR_VISIBLE] == len(blocks)
     assert np.array_equal(items, parity.expected_items(osc, blocks))
     lc = parity.LevelCache(osc)
-    assert parity.check_coefs(lc, items, coef, coef_sample) == []
-    maxd, nmis, tie, n = parity.check_texels(lc, blocks, tiles, texel_sample)
-    print("texels: max diff %d, %d of %d channels differ, worst tie distance %.2e" % (maxd, nmis, n, tie))
-    assert maxd <= 1 and tie < 0.01
+    if idct_mode != jpt.IDCT_FUSED_F32:   # (the fused decode writes texels only)
+        assert parity.check_coefs(lc, items, coef, coef_sample) == []
+    maxd, nmis, tie, dist, n = parity.check_texels(lc, blocks, tiles, texel_sample)
+    print("texels: max diff %d, %d of %d channels differ, worst tie distance %.2e (%.2f of its tolerance)"
+          % (maxd, nmis, n, dist, tie))
+    assert maxd <= 1 and tie <= 1.0
     imgs = parity.levels_from_tiles(osc, blocks, tiles)
     for g, f in zip(wl.views, frames):
         ref, bad = osc.resolve(g, wl.filter, imgs)

@@ -187,3 +187,103 @@ def test_lru_invariants(frames, cap):
         assert set(unew) == V - seen
         seen |= V
         resident_prev = R
+
+
+def test_lru_hand_example_with_frame_gaps():
+    """Hand-worked trace (Update Cache with a capacity): frames far apart, so
+    that ages exceed any small age cap; eviction must follow last use, not
+    block id.  Capacity 3."""
+    sim = oracle.LruSim(3)
+    assert sim.step(0, {10}) == ([10], [])
+    assert sim.step(500, {3}) == ([3], [])
+    assert sim.step(600, {7}) == ([7], [])
+    # f = 3000: resident 10 (used at 0), 3 (500), 7 (600); 10 is the oldest
+    # although its id is the largest
+    assert sim.step(3000, {5}) == ([5], [10])
+    # f = 10**6: two new blocks, 5 stays visible; 3 then 7 are the oldest
+    assert sim.step(10**6, {5, 1, 2}) == ([1, 2], [3, 7])
+    # equal last use: the smaller block id goes first
+    assert sim.step(10**6 + 1, {8}) == ([8], [1])
+    assert sim.step(4_000_000_000, {9}) == ([9], [2])
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.tuples(st.integers(1, 3_000_000), st.sets(st.integers(0, 40), max_size=12)), min_size=1,
+                max_size=10), st.integers(12, 30))
+def test_lru_oldest_first_with_large_gaps(steps, cap):
+    """Brute force per frame: the evicted blocks are the |new| - free
+    non-visible resident blocks of smallest (last use, id), for frame
+    numbers far apart."""
+    sim = oracle.LruSim(cap)
+    f = 0
+    last = {}
+    for gap, V in steps:
+        f += gap
+        R = set(last)
+        new = sorted(V - R)
+        free = cap - len(R)
+        need = max(0, len(new) - free)
+        keys = sorted((last[b], b) for b in R - V)
+        want_ev = sorted(b for _, b in keys[:need])
+        got_new, got_ev = sim.step(f, V)
+        assert got_new == new and got_ev == want_ev
+        for b in want_ev:
+            del last[b]
+        for b in V:
+            last[b] = f
+        assert dict(sim.last_used) == last
+
+
+def _level_image(rng, s, L):
+    return rng.integers(0, 256, (int(s.lev_h[L]), int(s.lev_w[L]), 3)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("frac,fx", [(0.25, 64), (0.75, 192), (1 / 512 - 2 ** -16, 0), (1 / 512, 1),
+                                     (1 / 512 + 2 ** -16, 1), (3 / 512 - 2 ** -16, 1), (3 / 512, 2),
+                                     (3 / 512 + 2 ** -16, 2), (1 - 2 ** -10, 256)])
+def test_bilinear_weights_at_general_fractions(small_scene, frac, fx):
+    """Closed form of the 8-bit horizontal weight f = floor(frac * 256 + 0.5)
+    (values written out by hand, ties at odd multiples of 1/512 rounding up):
+    with v at texel centres the pixel is (t0 (256 - f) + t1 f + 128) >> 8 per
+    channel, t0 = texel floor(s), t1 the next one (repeat-wrapped)."""
+    s = small_scene
+    rng = np.random.default_rng(8)
+    img = _level_image(rng, s, 0)
+    x, y = np.meshgrid(np.arange(64), np.arange(64))
+    u = ((x + 0.5 + frac) / 64).astype(np.float32)    # s = u*64 - 0.5 = x + frac, exact in fp32
+    assert np.all(u * np.float32(64) - np.float32(0.5) == (x + frac).astype(np.float32))
+    fb, bad = s.resolve(gb(u, (y + 0.5) / 64), BILINEAR, {0: img})
+    assert bad == 0
+    t0 = img.astype(np.int64)
+    t1 = np.roll(t0, -1, axis=1)
+    want = (t0 * (256 - fx) + t1 * fx + 128) >> 8
+    assert np.array_equal(oracle.unpack_frame(fb)[:, :, :3].astype(np.int64), want)
+
+
+def test_bilinear_weights_in_both_axes(small_scene):
+    """s = x + 1/4 and t = y + 3/4: weights 192/64 across, 64/192 down."""
+    s = small_scene
+    img = _level_image(np.random.default_rng(9), s, 0).astype(np.int64)
+    x, y = np.meshgrid(np.arange(64), np.arange(64))
+    fb, _ = s.resolve(gb((x + 0.75) / 64, (y + 1.25) / 64), BILINEAR, {0: img.astype(np.uint8)})
+    r = lambda a, dy, dx: np.roll(np.roll(a, -dy, axis=0), -dx, axis=1)
+    acc = (img * 192 * 64 + r(img, 0, 1) * 64 * 64 + r(img, 1, 0) * 192 * 192 + r(img, 1, 1) * 64 * 192)
+    assert np.array_equal(oracle.unpack_frame(fb)[:, :, :3].astype(np.int64), (acc + 32768) >> 16)
+
+
+@pytest.mark.parametrize("lod,t", [(1.3, 77), (1.7, 179), (2.0 + 1 / 512, 1), (1.0 + 1 / 1024, 0)])
+def test_trilinear_weight_at_non_dyadic_lod(small_scene, lod, t):
+    """t = floor(frac(lod) * 256 + 0.5) in fp32: lod 1.3 -> 76.8 -> 77, lod
+    1.7 -> 179.2 -> 179, a tie at 1/512 rounds up, 1/1024 rounds down; the
+    pixel is (a (256 - t) + b t + 128) >> 8 of the two levels' bilinear
+    results."""
+    s = small_scene
+    rng = np.random.default_rng(10)
+    lv = {L: _level_image(rng, s, L) for L in range(4)}
+    u = rng.random((8, 8)).astype(np.float32); v = rng.random((8, 8)).astype(np.float32)
+    lo = int(np.floor(lod))
+    tr, _ = s.resolve(gb(u, v, lod=np.float32(lod)), TRILINEAR, lv)
+    a, _ = s.resolve(gb(u, v, lod=float(lo)), BILINEAR, lv)
+    b, _ = s.resolve(gb(u, v, lod=float(lo + 1)), BILINEAR, lv)
+    A = oracle.unpack_frame(a)[..., :3].astype(int); B = oracle.unpack_frame(b)[..., :3].astype(int)
+    assert np.array_equal(oracle.unpack_frame(tr)[..., :3], (A * (256 - t) + B * t + 128) >> 8)
