@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ms/frame visible-block decode+resolve @1080p; Mblocks/s; fwd+bwd ms; HBM GB/s"
+# the arithmetic of the path: integer entropy decode, index and blends; fp32 IDCT and colour
+DTYPE = "int32+fp32"
 HBM_PEAK_GBS = 8000.0
 
 # HBM traffic per launch of a phase's kernel on the 1080p frame, from
@@ -99,6 +101,74 @@ def algorithmic_bytes(r, ctr):
     )
 
 
+def item_bits(r):
+    """Entropy-coded bits of each listed work item's MCU (from the index records)."""
+    import numpy as np
+    items = r.frame.work_items()
+    host = r.host
+    blocks = (items & 0x7FFFFFFF) >> 2
+    q = items & 3
+    lev = host.word_level[blocks >> 5]
+    out = np.zeros(len(items), np.int64)
+    for L in np.unique(lev):
+        inf = host.levels[int(L)].info
+        rec = host.levels[int(L)].records.view(np.uint32).reshape(-1, 16)
+        g = np.arange(inf.n_mcu) // 9; j = np.arange(inf.n_mcu) % 9
+        jm = np.maximum(j, 1) - 1
+        rel = np.where(j == 0, 0, (rec[g, 1 + jm // 2] >> (16 * (jm % 2))) & 0xFFFF)
+        starts = np.zeros(inf.n_mcu + 1, np.int64)
+        starts[:-1] = rec[g, 0].astype(np.int64) + rel
+        starts[-1] = inf.stream_bits
+        sel = lev == L
+        r_ = blocks[sel] - host.blk_base[int(L)]
+        bx = r_ % inf.blk_cols; by = r_ // inf.blk_cols
+        if inf.sampling == 444:
+            mx = 2 * bx + (q[sel] & 1); my = 2 * by + (q[sel] >> 1)
+            ok = (mx < inf.mcu_cols) & (my < inf.mcu_rows)
+            m = np.where(ok, my * inf.mcu_cols + mx, 0)
+            out[sel] = np.where(ok, starts[m + 1] - starts[m], 0)
+        else:
+            m = by * inf.mcu_cols + bx
+            out[sel] = starts[m + 1] - starts[m]
+    return out
+
+
+def chain_floor(r, steps):
+    """The decode's latency floor on this frame: the kernel run on the
+    frame's longest MCU alone (the frame cannot finish before that MCU's
+    symbol chain does), and on no item (launch and prologue), next to the
+    frame's own decode time."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    bits = item_bits(r)
+    n = len(bits)
+    i = int(np.argmax(bits))
+    work = r.frame.work[:n].clone()
+    ctr = r.frame.counters.clone()
+
+    def timed(k):
+        r.frame.counters[jpt.CTR_ITEMS] = k
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in ev:
+            e0.record()
+            r.decode()
+            e1.record()
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+    full = timed(n)
+    r.frame.work[0] = work[i]
+    alone = timed(1)
+    empty = timed(0)
+    r.frame.work[:n].copy_(work)
+    r.frame.counters.copy_(ctr)
+    torch.cuda.synchronize()
+    return {"longest_mcu_bits": int(bits[i]), "median_mcu_bits": int(np.median(bits)),
+            "decode_ms": round(full, 4), "longest_mcu_alone_ms": round(alone, 4), "no_item_ms": round(empty, 4),
+            "frac_of_floor": round(alone / full, 3)}
+
+
 def cpu_baseline(wl, budget_s=20.0):
     """The oracle as written (single thread): visible set, full sequential
     decode of every touched level, resolve.  Bounded sample: levels are
@@ -138,6 +208,56 @@ def cpu_baseline(wl, budget_s=20.0):
     sample = ("mark + resolve of the full frame; sequential decode of %d of %d touched levels (%.1f%% of their "
               "texels), decode time scaled by texel count" % (len(levels), len(touched), 100.0 * done_tex / tex_total))
     return {"value": round(ms, 1), "unit": "ms/frame", "cores": 1, "kind": "oracle", "sample": sample}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_ondemand_baseline(wl, gpu_ms, budget_s=15.0):
+    """The CPU on-demand baseline: the oracle's routines doing the paper's
+    per-frame method (mark, decode only the marked blocks' MCUs by random
+    access through the oracle's own per-MCU index, resolve), on one thread
+    and on all the host cores the box grants (at most 16).  The index is
+    recorded before timing.  Median over repeated frames within the budget."""
+    import numpy as np
+    import oracle
+    osc = oracle.Scene(wl.textures)
+    t0 = time.perf_counter()
+    od = oracle.OnDemand(osc)
+    log("CPU on-demand index recorded in %.1f s" % (time.perf_counter() - t0))
+    g = wl.views[0]
+    ref = None
+    out = {}
+    n_all = max(1, min(os.cpu_count() or 1, 16))
+    for threads in sorted({1, n_all}):
+        times, t_start = [], time.perf_counter()
+        while len(times) < 7 and (len(times) < 2 or time.perf_counter() - t_start < budget_s / 2):
+            f, t, n, bad = od.frame(g, wl.filter, threads)
+            if bad:
+                raise SystemExit("CPU on-demand baseline: %d bad pixels or MCUs" % bad)
+            if ref is None:
+                ref = f
+            elif not np.array_equal(f, ref):
+                raise SystemExit("CPU on-demand baseline differs between thread counts")
+            times.append(t)
+        med = np.median(np.array(times), axis=0) * 1000.0
+        out["threads_%d" % threads] = {"ms_per_frame": round(float(med.sum()), 2),
+                                       "mark_ms": round(float(med[0]), 2), "list_ms": round(float(med[1]), 3),
+                                       "decode_ms": round(float(med[2]), 2), "resolve_ms": round(float(med[3]), 2),
+                                       "frames": len(times)}
+    best = out["threads_%d" % n_all]["ms_per_frame"]
+    out.update({"unit": "ms/frame", "cores_all": n_all, "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+                "blocks_decoded": n, "kind": "oracle routines, on-demand (mark, random-access decode, resolve)",
+                "gpu_speedup_vs_all_cores": round(best / gpu_ms, 1)})
+    return out
 
 
 def time_graph(r, steps, warmup):
@@ -267,7 +387,8 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
                 "entropy": ab["compressed"] + int(ctr[jpt.CTR_NEW]) * 1024 if fused else ab["entropy"],
                 "idct": 0 if fused else ab["idct"], "resolve": ab["resolve"]}
     n_items = int(ctr[jpt.CTR_ITEMS]); n_du = n_items * 6
-    dec_ms = float(med[1] + med[2])
+    # the fused decode is one kernel: the "idct" phase between its two events is empty
+    dec_ms = float(med[1]) if fused else float(med[1] + med[2])
     # the dominant single kernel (mark+compact is two launches)
     single = [i for i, n in enumerate(PHASES) if n != "mark+compact"]
     dom = PHASES[max(single, key=lambda i: med[i])]
@@ -279,14 +400,14 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
     out = {
         "metric": METRIC, "value": round(ms_per_step, 4), "unit": "ms/frame", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": label, "decode": args.idct, "views": r.views.n, "pixels": r.views.n_pixels,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE,
+        "data": "synthetic", "config": {"workload": label, "decode": args.idct, "views": r.views.n, "pixels": r.views.n_pixels,
                    "visible_blocks": int(ctr[jpt.CTR_VISIBLE]), "decoded_blocks": int(ctr[jpt.CTR_NEW]),
                    "data_units": n_du},
         "gpu_ms_per_frame_median": round(float(np.median(gpu_frame)), 4),
         "cold_gpu_ms_per_frame_median": round(float(np.median(cold)), 4),
         "eager_ms_per_frame": round(eager_ms, 4),
-        "phases_ms_median": {n: round(float(m), 4) for n, m in zip(PHASES, med)},
+        "phases_ms_median": {n: (None if (fused and n == "idct") else round(float(m), 4)) for n, m in zip(PHASES, med)},
         "mblocks_per_s": round(n_du / (dec_ms * 1e-3) / 1e6, 1),
         # the entropy kernel is bound by its symbol chain, not by bandwidth:
         # entropy-coded bits of the decoded MCUs per second of the decode phase
@@ -294,6 +415,9 @@ def plain_form(args, wl, label, policy=0, n_slots=None):
         "hbm_gbps_algorithmic": round(ab["method"] / (float(np.median(gpu_frame)) * 1e-3) / 1e9, 1),
         "roofline": roof,
     }
+    if fused:
+        # the entropy kernel is bound by the latency of its longest symbol chains, not by a throughput
+        out["roofline"]["chain_floor"] = chain_floor(r, max(10, args.steps // 2))
     return r, out
 
 
@@ -419,7 +543,7 @@ def heavy_form(args, reps=None):
     phases = np.array([[pev[f][i].elapsed_time(pev[f][i + 1]) for i in range(3)] for f in range(nf)])
     return {"metric": METRIC, "value": round(float(med.mean()), 4), "unit": "ms/frame", "n_gpus": 1,
             "steps": reps * nf, "warmup": 0, "ms_per_step": round(1000.0 * wall / (reps * nf), 4),
-            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE,
             "data": "synthetic",
             "config": {"workload": wl.name + ", trilinear, LRU 2 GiB", "frames": nf, "repetitions": reps,
                        "pixels_per_frame": int(wl.views[0].size), "block_ids": int(r.scene.n_blocks)},
@@ -429,6 +553,167 @@ def heavy_form(args, reps=None):
                                 "decode": [round(float(x), 4) for x in phases[:, 1]],
                                 "resolve": [round(float(x), 4) for x in phases[:, 2]]},
             "frames_visible_new_evicted": counts}
+
+
+def paper_variants(args, wl, host):
+    """The paper's relative comparisons on the 1080p workload (Evaluation:
+    Performance, Linear Interpolation): per-phase GPU ms of eager frames for
+    nearest, bilinear and the single-MCU clamped bilinear (whose footprint is
+    the centre block alone), and for bilinear with mip mapping off."""
+    from paper_2510_08166_amd import jpt
+    out = {}
+    cases = (("nearest", jpt.FILTER_NEAREST, jpt.CACHE_NONE), ("bilinear", jpt.FILTER_BILINEAR, jpt.CACHE_NONE),
+             ("bilinear_clamped", jpt.FILTER_BILINEAR_CLAMPED, jpt.CACHE_NONE),
+             ("bilinear_mip_off", jpt.FILTER_BILINEAR | jpt.FILTER_MIP_OFF, jpt.CACHE_NONE),
+             # the paper's own cache: a hash map probed per tap
+             ("hash_nearest", jpt.FILTER_NEAREST, jpt.CACHE_HASH),
+             ("hash_bilinear", jpt.FILTER_BILINEAR, jpt.CACHE_HASH),
+             ("hash_bilinear_clamped", jpt.FILTER_BILINEAR_CLAMPED, jpt.CACHE_HASH))
+    for name, filt, policy in cases:
+        r = jpt.Renderer(wl.textures, wl.views, filt, device="cuda:0", host=host, idct_mode=IDCT_MODES[args.idct],
+                         policy=policy)
+        for _ in range(3):
+            r.render()
+        _, med = time_phases(r, max(10, args.steps // 2))
+        ctr = r.frame.counters_host()
+        if ctr[jpt.CTR_ERROR]:
+            raise SystemExit("%s: device error flags %x" % (name, ctr[jpt.CTR_ERROR]))
+        # (with the hash cache the timed frames after the first find their blocks resident)
+        out[name] = {"mark_ms": round(float(med[0]), 4), "decode_ms": round(float(med[1] + med[2]), 4),
+                     "resolve_ms": round(float(med[3]), 4), "frame_ms": round(float(med.sum()), 4),
+                     "visible_blocks": int(ctr[jpt.CTR_VISIBLE])}
+        del r
+    return out
+
+
+def motion_form(args, textures, reps, log_prefix="motion"):
+    """The paper's motion protocol (Evaluation: Caching): a camera turning 6
+    degrees per frame, a full turn every 60 frames, `reps` turns; per view
+    direction the median frame time over the turns, then the maximum over
+    the 60 directions (max-of-medians).  The scene is a room of textured
+    quads (the atrium stand-in) rendered each frame by the GPU geometry
+    pass; the timed frame is mark + decode + resolve (one graph launch), in
+    three configurations: no mip maps and no cache, mip maps, mip maps and
+    the paper's cache (evict every block a frame does not read)."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt, synth
+    W, H = 1920, 1080
+    tris = synth.room_scene(8, len(textures), tex_side=textures[0].width)
+    tris_t = torch.from_numpy(np.ascontiguousarray(tris).view(np.uint8).copy()).cuda()
+    host = jpt.HostScene(textures)
+    dirs = 60
+    cams = [synth.camera((0.0, 1.7, 0.0), 6.0 * d, -5.0, 90.0, W, H) for d in range(dirs)]
+    configs = (("no_mip_no_cache", jpt.FILTER_BILINEAR | jpt.FILTER_MIP_OFF, jpt.CACHE_NONE),
+               ("mip_no_cache", jpt.FILTER_BILINEAR, jpt.CACHE_NONE),
+               ("mip_cache", jpt.FILTER_BILINEAR, jpt.CACHE_EVICT_INVISIBLE),
+               ("mip_hash_cache", jpt.FILTER_BILINEAR, jpt.CACHE_HASH))
+    res = {"protocol": "6 deg/frame, %d directions, %d turns, max over directions of the median over turns" % (
+        dirs, reps), "pixels": W * H, "triangles": int(len(tris))}
+    side = torch.cuda.Stream()
+    for name, filt, policy in configs:
+        g0 = np.zeros((H, W), synth.GPIXEL_DTYPE)
+        r = jpt.Renderer(textures, [g0], filt, device="cuda:0", host=host, policy=policy,
+                         n_slots=None if policy == jpt.CACHE_NONE else 1 << 20, max_items=1 << 20,
+                         idct_mode=IDCT_MODES[args.idct])
+        side.wait_stream(torch.cuda.current_stream())
+        graph = r.capture(side)
+        times = np.zeros((reps, dirs))
+        geo = np.zeros((reps, dirs))
+        blocks = np.zeros(dirs)
+        with torch.cuda.stream(side):
+            if policy != jpt.CACHE_NONE:
+                r.cache.reset(r.scene, jpt.vp(side.cuda_stream))
+            # one warm-up turn
+            for d in range(dirs):
+                jpt.geometry_pass(r.scene, tris_t, cams[d], r.views, stream=jpt.vp(side.cuda_stream))
+                graph.launch()
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps * dirs)]
+            for k in range(reps):
+                for d in range(dirs):
+                    e = ev[k * dirs + d]
+                    e[0].record(side)
+                    jpt.geometry_pass(r.scene, tris_t, cams[d], r.views, stream=jpt.vp(side.cuda_stream))
+                    e[1].record(side)
+                    graph.launch()
+                    e[2].record(side)
+                    if k == reps - 1:
+                        side.synchronize()
+                        blocks[d] = r.frame.counters_host()[jpt.CTR_NEW]
+            side.synchronize()
+        ctr = r.frame.counters_host()
+        if ctr[jpt.CTR_ERROR]:
+            raise SystemExit("%s %s: device error flags %x" % (log_prefix, name, ctr[jpt.CTR_ERROR]))
+        for k in range(reps):
+            for d in range(dirs):
+                e = ev[k * dirs + d]
+                geo[k, d] = e[0].elapsed_time(e[1])
+                times[k, d] = e[1].elapsed_time(e[2])
+        graph.close()
+        med = np.median(times, axis=0)
+        res[name] = {"max_of_medians_ms": round(float(med.max()), 4), "mean_of_medians_ms": round(float(med.mean()), 4),
+                     "decoded_blocks_per_frame_mean": round(float(blocks.mean()), 1),
+                     "decoded_blocks_per_frame_max": int(blocks.max())}
+        res["geometry_pass_ms_median"] = round(float(np.median(geo)), 4)
+        log("%s %s: max of medians %.4f ms" % (log_prefix, name, med.max()))
+        del r
+    return res
+
+
+def bc1_form(args, wl, gpu_ms):
+    """The fixed-rate baseline (Background: BC1): the same textures encoded
+    as BC1 by our simple encoder, sampled by jpt_bc1_resolve over the 1080p
+    G-buffer (no mark, decode or cache); resolve time per frame and storage
+    against the JPEG pipeline's frame time and compressed size."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt, synth
+    t0 = time.perf_counter()
+    levels = [[(synth.bc1_encode(l), l.shape[1], l.shape[0]) for l in synth.mip_chain(synth.texture(t.seed, t.width,
+                                                                                                      t.height), len(t.jpegs))]
+              for t in wl.textures]
+    log("BC1 textures encoded in %.1f s" % (time.perf_counter() - t0))
+    sc = jpt.Bc1Scene(levels)
+    views = jpt.Views(wl.views)
+    for _ in range(5):
+        jpt.bc1_resolve(sc, views, wl.filter)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in ev:
+        e0.record()
+        jpt.bc1_resolve(sc, views, wl.filter)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    jpeg_bytes = sum(len(j) for t in wl.textures for j in t.jpegs)
+    return {"resolve_ms_per_frame": round(ms, 4), "jpeg_pipeline_ms_per_frame": gpu_ms,
+            "bc1_bytes": sc.bytes, "jpeg_file_bytes": jpeg_bytes,
+            "bc1_bits_per_texel": round(8.0 * sc.bytes / sum(w * h for t in levels for _, w, h in t), 3)}
+
+
+def other_forms(args):
+    """The batched (16 views, one graph launch) and differentiable (fwd+bwd)
+    forms on their own workloads, timed the same way as their own bench
+    lines but without the tuner and the per-view comparison, reported as
+    extra keys of the default line."""
+    from paper_2510_08166_amd.synth import configs
+    t0 = time.perf_counter()
+    d = diff_form(args)
+    res = {"diff1080": {"workload": d["config"]["workload"], "fwd_bwd_ms_per_step": d["value"],
+                        "fwd_ms_median": d["fwd_ms_median"], "bwd_ms_median": d["bwd_ms_median"],
+                        "work_items": d["config"]["work_items"]}}
+    log("diff1080 done in %.1f s" % (time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    wl = configs.batched16(log=log)
+    log("batched16 generated in %.1f s" % (time.perf_counter() - t0))
+    r, b = plain_form(args, wl, "batched16")
+    res["batched16"] = {"workload": wl.name, "ms_per_frame": b["value"],
+                        "gpu_ms_per_frame_median": b["gpu_ms_per_frame_median"],
+                        "ms_per_view": round(b["value"] / r.views.n, 4), "views": r.views.n,
+                        "pixels": r.views.n_pixels, "decoded_blocks": b["config"]["decoded_blocks"],
+                        "data_units": b["config"]["data_units"], "phases_ms_median": b["phases_ms_median"],
+                        "mblocks_per_s": b["mblocks_per_s"], "hbm_gbps_algorithmic": b["hbm_gbps_algorithmic"],
+                        "roofline": b["roofline"]}
+    return res
 
 
 def batched_extras(args, r, out):
@@ -515,8 +800,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="frame1080", choices=["frame1080", "batched16", "diff1080", "heavy"])
+    ap.add_argument("--workload", default="frame1080",
+                    choices=["frame1080", "batched16", "diff1080", "heavy", "motion"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--motion-reps", type=int, default=20,
+                    help="turns of the 6 deg/frame motion protocol (the paper uses 100)")
+    ap.add_argument("--no-extra-forms", action="store_true",
+                    help="frame1080 only: skip the batched16 and diff1080 figures added to the line")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--idct", default="fused", choices=["fused", "mfma", "scalar"],
@@ -537,6 +827,15 @@ def main():
     if args.workload == "heavy":
         print(json.dumps(heavy_form(args)), flush=True)
         return
+    if args.workload == "motion":
+        wl = configs.frame1080()
+        m = motion_form(args, wl.textures, reps=args.motion_reps)
+        print(json.dumps({"metric": METRIC, "value": m["mip_cache"]["max_of_medians_ms"], "unit": "ms/frame",
+                          "n_gpus": 1, "steps": 60 * args.motion_reps, "warmup": 60, "higher_is_better": False,
+                          "scaling": "weak", "vs_baseline": None, "dtype": DTYPE, "data": "synthetic",
+                          "config": {"workload": "room of 480 quads over the 1080p texture set, 1920x1080, bilinear, "
+                                                 "6 deg/frame, evict-invisible cache"}, "motion": m}), flush=True)
+        return
     t0 = time.perf_counter()
     if args.workload == "frame1080":
         wl = configs.frame1080()
@@ -553,6 +852,18 @@ def main():
     if args.workload == "frame1080" and not args.no_cpu_baseline:
         log("timing the CPU oracle (budget %.0f s)" % args.cpu_budget)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        log("timing the CPU on-demand baseline")
+        out["cpu_ondemand_baseline"] = cpu_ondemand_baseline(wl, out["value"])
+    if args.workload == "frame1080" and not args.no_extra_forms:
+        host = r.host
+        del r
+        t0 = time.perf_counter()
+        out["paper_variants"] = paper_variants(args, wl, host)
+        out["bc1_baseline"] = bc1_form(args, wl, out["gpu_ms_per_frame_median"])
+        out["motion"] = motion_form(args, wl.textures, reps=args.motion_reps)
+        log("paper variants, BC1 and motion legs in %.1f s" % (time.perf_counter() - t0))
+        del host
+        out["other_forms"] = other_forms(args)
     print(json.dumps(out), flush=True)
 
 

@@ -72,9 +72,24 @@ typedef int32_t jpt_status;
 #define JPT_FILTER_NEAREST 0u
 #define JPT_FILTER_BILINEAR 1u
 #define JPT_FILTER_TRILINEAR 2u
+/* The paper's resolve clamped to a single MCU (Evaluation: Linear
+ * Interpolation; Method: Resolve): bilinear weights, but a tap outside the
+ * 16x16 block of the texel under the sample point (the nearest filter's
+ * texel) reads that texel's column or row instead.  Its footprint is that
+ * one block, so marking with it is the paper's centre-only marking. */
+#define JPT_FILTER_BILINEAR_CLAMPED 3u
+/* OR'd into any filter: mip mapping off, every pixel samples level 0 (the
+ * paper's performance table without mip maps). */
+#define JPT_FILTER_MIP_OFF 0x100u
 
 #define JPT_CACHE_NONE 0u       /* each frame decodes every visible block; slot = rank */
 #define JPT_CACHE_LRU 1u        /* frame-granular LRU with a slot capacity */
+#define JPT_CACHE_EVICT_INVISIBLE 2u  /* the paper's Update Cache: after each frame every resident block the
+                                         frame did not read is evicted (the LRU arrays, same reset) */
+#define JPT_CACHE_HASH 3u       /* the paper's Texture Block Cache as it builds it: a hash map from a 32-bit
+                                   key (16-bit block index, 13-bit texture, 3-bit level) to a slot, filled by
+                                   atomicCAS in mark, probed per tap in resolve, every block a frame does not
+                                   read evicted (see jpt_cache.hash) */
 
 #define JPT_IDCT_MFMA_F16 0u    /* 64x64 basis on MFMA, split-fp16 operands, fp32 accumulate */
 #define JPT_IDCT_SCALAR_F32 1u  /* separable fp32 row/column IDCT on the vector ALUs */
@@ -90,12 +105,14 @@ typedef int32_t jpt_status;
 #define JPT_CTR_ERROR_ITEM 4    /* smallest failing work-item index (0xFFFFFFFF = none) */
 #define JPT_CTR_EVICTED 5       /* blocks evicted this frame (LRU) */
 #define JPT_CTR_RESIDENT 6      /* resident blocks after this frame (LRU) */
+#define JPT_CTR_GRAD_MAX 7      /* jpt_backward: fp32 bits of the largest |dL/dframe| it scaled by */
 #define JPT_N_COUNTERS 16u
 
 #define JPT_ERR_CORRUPT 1u      /* invalid code, > 64 coefficients, or MCU span mismatch */
 #define JPT_ERR_CAPACITY 2u     /* work list or cache slots exhausted */
 #define JPT_ERR_PIXEL 4u        /* G-buffer pixel with bad texture id or coordinates */
 #define JPT_ERR_INTERNAL 8u     /* reserved: a bounded device-side wait gave up (no kernel of this version waits) */
+#define JPT_ERR_GRAD 16u        /* jpt_backward: a non-finite entry in dL/dframe */
 
 #define JPT_SLOT_NONE 0xFFFFFFFFu
 #define JPT_TEX_BACKGROUND 0xFFFFFFFFu
@@ -143,13 +160,25 @@ typedef struct jpt_level_info {
     uint8_t huff_bits[4][16];     /* BITS (codes per length 1..16): DC luma, AC luma, DC chroma, AC chroma */
     uint8_t huff_vals[4][256];    /* HUFFVAL of each table */
     uint16_t huff_nvals[4];
-    uint16_t reserved0[2];
+    uint16_t index_kind;          /* JPT_INDEX_SPLICED / JPT_INDEX_PREDICTORS */
+    uint16_t reserved0;
     double index_bits_per_mcu;    /* 160/9 */
     double dc_bits_per_mcu;       /* 36 */
     double overhead_bpp_bound;    /* (index + dc bits per MCU) / MCU texels */
     double overhead_bpp_effective;/* same minus the removed DC bits, over the level's MCU texels */
     double stored_bpp;            /* (records*64*8 + stream_bits) / (width*height) */
 } jpt_level_info;
+
+/* The two readings of the paper's index.  JPT_INDEX_SPLICED: the stream and
+ * records described above (absolute DCs, DC codes spliced out).
+ * JPT_INDEX_PREDICTORS: the level's entropy-coded segment untouched (only
+ * de-stuffed), the records' offsets pointing into it and their 12-bit
+ * fields holding the DC predictors (Y, Cb, Cr) in force when each MCU
+ * starts; every data unit then decodes its DC difference as in T.81.  Any
+ * baseline decoder can still read the stream; the overhead is the paper's
+ * bound (53.78 bits per MCU) with nothing removed. */
+#define JPT_INDEX_SPLICED 0u
+#define JPT_INDEX_PREDICTORS 1u
 
 /* Parse a baseline JPEG (SOF0, 8-bit, 3 components Y Cb Cr with Cb and Cr
  * sharing quant and Huffman tables, 4:2:0 or 4:4:4, one interleaved scan,
@@ -165,6 +194,13 @@ typedef struct jpt_level_info {
  * bits, stream above 2^32-1 bits), JPT_E_BUFSIZE. */
 jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level_info *info, uint32_t *stream_out,
                            size_t stream_cap_words, uint8_t *records_out, size_t records_cap_bytes);
+
+/* jpt_build_index with the index reading chosen by `kind`
+ * (JPT_INDEX_SPLICED is jpt_build_index).  Errors: as jpt_build_index, and
+ * JPT_E_ARG for an unknown kind. */
+jpt_status jpt_build_index_ex(const uint8_t *jpeg, size_t len, uint32_t kind, jpt_level_info *info,
+                              uint32_t *stream_out, size_t stream_cap_words, uint8_t *records_out,
+                              size_t records_cap_bytes);
 
 /* Decode tables for the GPU entropy decoder, built from info's Huffman
  * tables (the paper's per-code matching loop replaced by table lookup).
@@ -185,9 +221,10 @@ jpt_status jpt_layout(const jpt_level_info *infos, uint32_t n_levels, uint32_t *
  * Device-side descriptors (arrays of these live in device memory)
  * ------------------------------------------------------------------ */
 typedef struct jpt_level_desc {   /* 64 bytes */
-    uint64_t stream;              /* device address of the spliced stream (u32 words) */
+    uint64_t stream;              /* device address of the level's stream (u32 words) */
     uint64_t records;             /* device address of the 64-byte records */
-    uint64_t stream_bits;
+    uint32_t stream_bits;
+    uint32_t index_kind;          /* JPT_INDEX_SPLICED / JPT_INDEX_PREDICTORS */
     uint32_t width, height;
     uint32_t blk_cols, blk_rows;
     uint32_t mcu_cols, n_mcu;
@@ -228,8 +265,10 @@ typedef struct jpt_scene {        /* host struct holding device pointers */
     const uint16_t *quant;            /* n_quant * 128, zigzag, [luma 64][chroma 64] */
     uint32_t n_levels, n_textures, n_tablesets, n_quant;
     uint32_t n_blocks;                /* multiple of 32, <= 2^29 */
-    uint32_t reserved;
+    uint32_t flags;                   /* JPT_SCENE_*: set JPT_SCENE_PREDICTOR_INDEX if any level uses
+                                         JPT_INDEX_PREDICTORS (its MCUs fail to decode otherwise) */
 } jpt_scene;
+#define JPT_SCENE_PREDICTOR_INDEX 1u
 
 typedef struct jpt_view {         /* host struct holding device pointers */
     const jpt_gpixel *gbuf;       /* height rows of pitch pixels */
@@ -278,7 +317,16 @@ typedef struct jpt_cache {
     uint32_t *meta;               /* JPT_CACHE_META_WORDS: stack top, eviction plan, age histograms (LRU) */
     uint32_t *tie_mask;           /* n_blocks/32 words: scratch of the eviction (LRU) */
     uint32_t n_slots;
-    uint32_t policy;              /* JPT_CACHE_NONE / JPT_CACHE_LRU */
+    uint32_t policy;              /* JPT_CACHE_* */
+    uint32_t *hash;               /* JPT_CACHE_HASH: 2 * n_buckets words, bucket i = (key, value) at
+                                     [2i, 2i + 1]; value = slot | bit 31 when read this frame.  That policy
+                                     also uses texels, slot_of (written for each frame's new blocks, for
+                                     the decoder), owner (the key in each slot), free_stack and meta, and
+                                     takes 4:2:0 levels of at most 65,536 blocks, 8,191 textures of at most
+                                     8 levels (the key's fields); other pixels raise JPT_ERR_PIXEL.  The
+                                     queue order of its work items is the order of insertion. */
+    uint32_t n_buckets;           /* a power of two >= 2 n_slots */
+    uint32_t reserved;
 } jpt_cache;
 
 /* Empty an LRU cache: every slot free, no block resident.  Device call on
@@ -339,6 +387,21 @@ jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32
 jpt_status jpt_decode_blocks(const jpt_scene *scene, jpt_frame *frame, jpt_cache *cache, uint32_t idct_mode,
                              const jpt_tuning *tuning, void *stream);
 
+/* Reduced-resolution decode (paper: Discussion, lower resolutions from the
+ * DC and the first ACs instead of stored mip levels).  For every work item
+ * of the frame (as listed by jpt_mark_blocks, or written by the caller into
+ * frame->work with counters[JPT_CTR_ITEMS]): entropy-decode its MCU, then
+ * form its texels at scale 1/2^scale_log2 (1..3): each data unit's N x N
+ * samples (N = 8 >> scale_log2) by the N-point inverse DCT of its top-left
+ * N x N dequantised coefficients with the 8-point scaling (N = 1: the
+ * block mean), +128 and clamp, chroma over 2x2 luma samples, colour with
+ * one rounding.  texels_out: device memory, (16 >> scale_log2)^2 RGBA8
+ * texels per work item, row-major (a 4:4:4 item fills the first
+ * (8 >> scale_log2)^2); failed items get JPT_TEXEL_INVALID.  No cache slot
+ * is used.  Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_decode_reduced(const jpt_scene *scene, jpt_frame *frame, uint32_t scale_log2, uint32_t *texels_out,
+                              const jpt_tuning *tuning, void *stream);
+
 /* Entropy decode only (the first half of jpt_decode_blocks): fills
  * frame->coef for the listed work items.  Errors: JPT_E_ARG, JPT_E_HIP. */
 jpt_status jpt_entropy_decode(const jpt_scene *scene, jpt_frame *frame, const jpt_tuning *tuning, void *stream);
@@ -357,6 +420,68 @@ jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *c
  * Errors: JPT_E_ARG (also a cache of 0 slots), JPT_E_HIP. */
 jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                        const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+/* ------------------------------------------------------------------ *
+ * Geometry pass: the G-buffer the method starts from (paper: Method, the
+ * pass before Mark, which writes texture coordinates, texture ids and mip
+ * map levels), rendered on the GPU from textured triangles.
+ * ------------------------------------------------------------------ */
+typedef struct jpt_triangle {     /* 80 bytes */
+    float p0[3], p1[3], p2[3];    /* vertices */
+    float uv0[2], uv1[2], uv2[2]; /* texture coordinates of the vertices */
+    uint32_t tex;                 /* texture id */
+    uint32_t reserved[4];
+} jpt_triangle;
+
+typedef struct jpt_camera {       /* 64 bytes, passed by value to the kernel */
+    float eye[3];                 /* ray origin */
+    float fwd[3], right[3], up[3];/* pixel (x, y) of a W x H view looks along fwd + sx right + sy up, */
+    float tan_half_x, tan_half_y; /* sx = (2 (x + 0.5) / W - 1) tan_half_x, sy = (1 - 2 (y + 0.5) / H) tan_half_y */
+    float reserved[2];
+} jpt_camera;
+
+/* Every pixel of a width x height view takes the nearest triangle its centre
+ * ray hits (smallest t > 0; on equal t the lower index) and writes
+ * gbuf[y * pitch + x] = {u, v, tex, lod}: uv the hit's barycentric blend of
+ * the vertices' uv, lod = log2 of the larger texel footprint, in texels of
+ * the texture's level 0 (scene->textures), of the rays one pixel to the
+ * right and one pixel down met with the hit triangle's plane.  Pixels with
+ * no hit get tex = JPT_TEX_BACKGROUND.  fp32 arithmetic.  tris: device
+ * memory, n_tris entries; cam: host struct; gbuf: device memory.
+ * Errors: JPT_E_ARG, JPT_E_HIP. */
+jpt_status jpt_geometry_pass(const jpt_scene *scene, const jpt_triangle *tris, uint32_t n_tris,
+                             const jpt_camera *cam, uint32_t width, uint32_t height, uint32_t pitch,
+                             jpt_gpixel *gbuf, void *stream);
+
+/* ------------------------------------------------------------------ *
+ * Fixed-rate baseline (paper: Background, BC1): textures stored as BC1
+ * blocks, sampled directly by the resolve with no mark, decode or cache.
+ * A level's blocks: 8 bytes per 4x4 texels, row-major, little-endian:
+ * colour 0 and colour 1 (RGB565, u16), then 16 two-bit indices, texel
+ * (i, j) of the block (column i, row j) at bits 2 (4 j + i).  Endpoints
+ * widen to 8 bits by bit replication; palette {c0, c1, (2 c0 + c1 + 1) / 3,
+ * (c0 + 2 c1 + 1) / 3} if colour 0 > colour 1, else {c0, c1,
+ * (c0 + c1 + 1) / 2, black}, per channel in integers.
+ * ------------------------------------------------------------------ */
+typedef struct jpt_bc1_level {    /* 24 bytes */
+    const uint8_t *blocks;        /* device memory, 8-byte aligned */
+    uint32_t width, height;
+    uint32_t blocks_per_row;      /* ceil(width / 4) */
+    uint32_t reserved;
+} jpt_bc1_level;
+
+typedef struct jpt_bc1_scene {    /* host struct holding device pointers */
+    const jpt_bc1_level *levels;  /* n_levels, texture by texture, level 0 first */
+    const jpt_texture_desc *textures;
+    uint32_t n_levels, n_textures;
+} jpt_bc1_scene;
+
+/* Every pixel of every view with the level selection, taps and integer
+ * weights of jpt_resolve (JPT_FILTER_NEAREST / BILINEAR / TRILINEAR,
+ * optionally JPT_FILTER_MIP_OFF) over the BC1 texels.
+ * Errors: JPT_E_ARG (also JPT_FILTER_BILINEAR_CLAMPED), JPT_E_HIP. */
+jpt_status jpt_bc1_resolve(const jpt_bc1_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                           void *stream);
 
 /* ------------------------------------------------------------------ *
  * Batched form: one frame over all views (jpt_mark_blocks, then
@@ -420,10 +545,15 @@ jpt_status jpt_fwd_float(const jpt_scene *scene, const jpt_view *views, uint32_t
                          float *texel_f, float *frame_f, void *stream);
 
 /* Backward: dframe = dL/dframe_f -> dF = dL/dF.  dtexel is scratch of
- * 768 int64 per slot as texel_f (texel gradients in fixed point, 2^-32
- * units, summed with integer atomics so that the result does not depend on
- * their order); only the listed items' slots are cleared and used.
- * Errors: JPT_E_ARG (also n_slots >= 2^24), JPT_E_HIP. */
+ * 768 int64 per slot as texel_f: texel gradients in fixed point, summed
+ * with integer atomics so that the result does not depend on their order.
+ * The unit is 2^-s with s chosen per call from m = max |dframe| (kept in
+ * counters[JPT_CTR_GRAD_MAX] as fp32 bits) so that every tap's product
+ * stays below 2^36 units: sums are exact for up to 2^27 taps per texel and
+ * each product is rounded to m 2^-37, at any scale of the loss.  Only the
+ * listed items' slots are cleared and used.  A non-finite dframe entry
+ * raises JPT_ERR_GRAD.  Errors: JPT_E_ARG (also n_slots >= 2^24),
+ * JPT_E_HIP. */
 jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                         const jpt_frame *frame, const jpt_cache *cache, const float *dframe, int64_t *dtexel,
                         float *dF, uint32_t n_rows, void *stream);

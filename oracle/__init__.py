@@ -26,7 +26,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-NEAREST, BILINEAR, TRILINEAR = 0, 1, 2
+NEAREST, BILINEAR, TRILINEAR, BILINEAR_CLAMPED = 0, 1, 2, 3
+NO_MIP = 0x100   # OR'd into a filter: every pixel samples level 0
 BACKGROUND = 0xFFFFFFFF
 INVALID_TEXEL = 0xFFFF00FF
 # zigzag scan position -> natural index (T.81 Figure A.6), for tests that
@@ -39,8 +40,10 @@ ZIGZAG = np.array([0, 1, 8, 16, 9, 2, 3, 10, 17, 24, 32, 25, 18, 11, 4, 5, 12, 1
 def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+                               "-o", tmp, os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "ondemand.c"),
+                               os.path.join(_HERE, "geometry.c"), os.path.join(_HERE, "bc1.c"),
+                               "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -61,9 +64,11 @@ def lib():
             L.orc_decode_seq.argtypes = [vp, vp, vp, vp, vp]
             L.orc_decode_mcu_at.argtypes = [vp, u64, vp, vp, vp]
             L.orc_decode_stripped_mcu.argtypes = [vp, vp, u64, u64, vp, u64, ctypes.c_uint32, vp, vp]
+            L.orc_decode_predicted_mcu.argtypes = [vp, vp, u64, u64, vp, u64, ctypes.c_uint32, vp, vp]
             L.orc_idct.argtypes = [vp, vp]
             L.orc_pixels.argtypes = [vp, vp, vp, vp]
             L.orc_mcu_pixels.argtypes = [vp, vp, vp, vp]
+            L.orc_mcu_reduced.argtypes = [vp, vp, i32, vp, vp]
             L.orc_scene_layout.restype = u64
             L.orc_scene_layout.argtypes = [i32, vp, vp, vp]
             L.orc_mark.restype = i64
@@ -72,6 +77,11 @@ def lib():
             L.orc_resolve.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i64, i32, vp, vp]
             L.orc_taps.restype = i64
             L.orc_taps.argtypes = [i32, vp, vp, vp, vp, vp, i64, i32, vp, vp, vp, vp]
+            L.orc_geometry.argtypes = [vp, i64, vp, i32, i32, vp, vp, i32, vp, vp]
+            L.orc_bc1_decode.argtypes = [vp, i32, i32, vp]
+            L.orc_ondemand_frame.restype = i64
+            L.orc_ondemand_frame.argtypes = [i32, vp, vp, i32, vp, vp, vp, u64, vp, vp, vp, vp, vp, i64, i32, vp,
+                                             vp, vp, i32, vp, vp]
             _lib = L
     return _lib
 
@@ -134,6 +144,15 @@ class Jpeg:
                                            len(records) // 64, int(m), _p(out), ctypes.byref(end))
         return rc, out, end.value
 
+    def decode_predicted_mcu(self, words: np.ndarray, stream_bits: int, records: np.ndarray, m: int):
+        out = np.zeros((self.n_du, 64), np.int16)
+        end = ctypes.c_uint64(0)
+        words = np.ascontiguousarray(words, np.uint32)
+        records = np.ascontiguousarray(records, np.uint8)
+        rc = lib().orc_decode_predicted_mcu(self.h, _p(words), len(words), int(stream_bits), _p(records),
+                                            len(records) // 64, int(m), _p(out), ctypes.byref(end))
+        return rc, out, end.value
+
     def pixels(self, coef, want_f64=False):
         coef = np.ascontiguousarray(coef, np.int16)
         rgb = np.zeros((self.height, self.width, 3), np.uint8)
@@ -148,6 +167,17 @@ class Jpeg:
         f = np.zeros((ms, ms, 3), np.float64) if want_f64 else None
         lib().orc_mcu_pixels(self.h, _p(c), _p(rgb), _p(f))
         return (rgb, f) if want_f64 else rgb
+
+
+def mcu_reduced(j: "Jpeg", coef_mcu, scale_log2: int, want_f64=False):
+    """orc_mcu_reduced: an MCU's texel tile at 1/2^scale_log2 resolution."""
+    ms = (16 if j.sampling == 420 else 8) >> scale_log2
+    c = np.ascontiguousarray(coef_mcu, np.int16)
+    rgb = np.zeros((ms, ms, 3), np.uint8)
+    f = np.zeros((ms, ms, 3), np.float64) if want_f64 else None
+    if lib().orc_mcu_reduced(j.h, _p(c), int(scale_log2), _p(rgb), _p(f)) != 0:
+        raise OracleError("orc_mcu_reduced: bad arguments")
+    return (rgb, f) if want_f64 else rgb
 
 
 def idct(F: np.ndarray) -> np.ndarray:
@@ -244,6 +274,70 @@ class Scene:
         return frame, vis, bad
 
 
+class OnDemand:
+    """The CPU on-demand baseline over a Scene (orc_ondemand_frame): the
+    per-MCU index (start bit and DC predictors of every MCU of every level)
+    is recorded once by a sequential decode, outside any timing; each frame
+    then marks, decodes only the MCUs of the marked blocks by random access,
+    and resolves, on n threads."""
+
+    def __init__(self, scene: Scene):
+        self.s = scene
+        n = len(scene.jpegs)
+        self._bits, self._pred, self._img = [], [], []
+        for j in scene.jpegs:
+            _, mb, pred, _ = j.decode()
+            self._bits.append(mb)
+            self._pred.append(np.ascontiguousarray(pred.reshape(-1)))
+            self._img.append(np.zeros((j.height, j.width, 3), np.uint8))
+        self._jp = (ctypes.c_void_p * n)(*[j.h for j in scene.jpegs])
+        self._bp = (ctypes.c_void_p * n)(*[a.ctypes.data for a in self._bits])
+        self._pp = (ctypes.c_void_p * n)(*[a.ctypes.data for a in self._pred])
+        self._ip = (ctypes.c_void_p * n)(*[a.ctypes.data for a in self._img])
+        self._vis = np.zeros(scene.n_blocks, np.uint8)
+        self._list = np.zeros(max(1, scene.n_blocks), np.uint32)
+
+    def frame(self, g: np.ndarray, filt: int, threads: int = 1):
+        """(frame u32, seconds of mark / listing / decode / resolve, blocks decoded, bad count)."""
+        s = self.s
+        g = np.ascontiguousarray(g)
+        out = np.zeros(g.shape, np.uint32)
+        times = np.zeros(4, np.float64)
+        nd = ctypes.c_uint64(0)
+        bad = lib().orc_ondemand_frame(len(s.textures), _p(s.tex_first), _p(s.tex_count), len(s.jpegs),
+                                       _p(s.lev_w), _p(s.lev_h), _p(s.blk_base), s.n_blocks,
+                                       ctypes.cast(self._jp, ctypes.c_void_p), ctypes.cast(self._bp, ctypes.c_void_p),
+                                       ctypes.cast(self._pp, ctypes.c_void_p), ctypes.cast(self._ip, ctypes.c_void_p),
+                                       _p(g), g.size, filt, _p(out), _p(self._vis), _p(self._list), int(threads),
+                                       _p(times), ctypes.byref(nd))
+        if bad < 0:
+            raise OracleError("orc_ondemand_frame: bad arguments")
+        return out, times, int(nd.value), int(bad)
+
+
+def geometry(tris: np.ndarray, cam: np.ndarray, W: int, H: int, tex_w, tex_h, want_tri=False):
+    """The geometry pass by definition (orc_geometry): tris a structured
+    array of the triangle layout, cam one camera record; returns the
+    G-buffer (H, W) (and the hit triangle per pixel)."""
+    from paper_2510_08166_amd.synth import GPIXEL_DTYPE
+    tris = np.ascontiguousarray(tris)
+    cam = np.ascontiguousarray(cam)
+    tw = np.ascontiguousarray(tex_w, np.int32); th = np.ascontiguousarray(tex_h, np.int32)
+    g = np.zeros((H, W), GPIXEL_DTYPE)
+    hit = np.zeros((H, W), np.int32)
+    lib().orc_geometry(_p(tris), len(tris), _p(cam), W, H, _p(tw), _p(th), len(tw), _p(g), _p(hit))
+    return (g, hit) if want_tri else g
+
+
+def bc1_decode(blocks: bytes, w: int, h: int) -> np.ndarray:
+    """A BC1 image by definition (orc_bc1_decode): (h, w, 3) uint8."""
+    b = np.frombuffer(blocks, np.uint8)
+    assert len(b) >= ((w + 3) // 4) * ((h + 3) // 4) * 8
+    out = np.zeros((h, w, 3), np.uint8)
+    lib().orc_bc1_decode(_p(np.ascontiguousarray(b)), w, h, _p(out))
+    return out
+
+
 def unpack_frame(frame: np.ndarray) -> np.ndarray:
     f = np.ascontiguousarray(frame, np.uint32)
     return f.view(np.uint8).reshape(f.shape + (4,))
@@ -283,3 +377,24 @@ class LruSim:
         for b in new:
             self.last_used[b] = frame_no
         return new, evicted
+
+
+class EvictInvisibleSim:
+    """The paper's cache update (Method: Update Cache): after each frame every
+    cached block that the frame did not read is evicted; blocks read in
+    consecutive frames stay and are not decoded again.  Per frame with
+    visible set V: new = V - R, evicted = R - V, R := V."""
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity
+        self.resident: set[int] = set()
+
+    def step(self, visible) -> tuple[list, list]:
+        V = set(int(b) for b in visible)
+        if len(V) > self.capacity:
+            raise OracleError("visible set exceeds the cache capacity")
+        new = sorted(V - self.resident)
+        evicted = sorted(self.resident - V)
+        self.resident = V
+        return new, evicted
+

@@ -352,6 +352,31 @@ int orc_decode_stripped_mcu(const orc_jpeg *j, const uint32_t *words, uint64_t n
     return b.overrun ? ORC_E_CORRUPT : ORC_OK;
 }
 
+/* ------------------------------------- predictor-index random access -- */
+/* The index reading with the segment untouched: the record's offsets point
+ * into the original (de-stuffed) segment and its 12-bit fields hold the DC
+ * predictors in force when each MCU starts; the MCU is then the plain F.2
+ * MCU body started there with those predictors. */
+int orc_decode_predicted_mcu(const orc_jpeg *j, const uint32_t *words, uint64_t n_words, uint64_t stream_bits,
+                             const uint8_t *records, uint64_t n_records, uint32_t m, int16_t *out,
+                             uint64_t *end_bit) {
+    if (!j || !words || !records || !out || m >= (uint32_t)j->n_mcu) return ORC_E_ARG;
+    uint64_t g = m / 9, r = m % 9;
+    if (g >= n_records || stream_bits > n_words * 32) return ORC_E_ARG;
+    const uint8_t *rec = records + g * 64;
+    uint64_t start = rec_bits(rec, 0, 32);
+    if (r) start += rec_bits(rec, 32 + 16 * (int)(r - 1), 16);
+    int32_t pred[3];
+    for (int c = 0; c < 3; c++) {
+        int32_t v = (int32_t)rec_bits(rec, 160 + 12 * (int)(3 * r + c), 12);
+        pred[c] = v >= 2048 ? v - 4096 : v;
+    }
+    bits_t b = {NULL, words, stream_bits, start, 0};
+    int e = decode_mcu(j, &b, pred, out, NULL);
+    if (end_bit) *end_bit = b.pos;
+    return e;
+}
+
 /* --------------------------------------------------------------- IDCT -- */
 #define ORC_PI 3.14159265358979323846
 
@@ -407,6 +432,62 @@ static void mcu_texels(const orc_jpeg *j, const int16_t *cm, uint8_t *rgb, doubl
                 if (rgb) rgb[o] = (uint8_t)clampd(floor(rgbv[c] + 0.5), 0.0, 255.0);
             }
         }
+}
+
+/* Reduced-resolution texels of one MCU (the paper's Discussion: lower
+ * resolutions from the DC and the first ACs instead of stored mip levels):
+ * each data unit's N x N samples, N = 8 >> s, by the N-point inverse DCT of
+ * its top-left N x N coefficients with the 8-point scaling,
+ * r(x,y) = 1/4 sum_{u,v<N} C(u) C(v) F(v,u) cos((2x+1)u pi/2N) cos((2y+1)v pi/2N)
+ * (N = 1: the block mean F00/8), then as mcu_texels: +128 and clamp, chroma
+ * replicated over 2x2 luma samples (4:2:0), colour with a single rounding.
+ * out_rgb: the (16 >> s) or (8 >> s) square tile, 3 bytes per texel. */
+static void mcu_reduced(const orc_jpeg *j, const int16_t *cm, int s, uint8_t *rgb, double *f64) {
+    const int N = 8 >> s, ms = (j->sampling == 420 ? 16 : 8) >> s;
+    double samp[6][64];
+    for (int d = 0; d < j->n_du; d++) {
+        int c = comp_of_du(j, d);
+        const uint16_t *q = j->qt[j->comp_tq[c]];
+        for (int y = 0; y < N; y++)
+            for (int x = 0; x < N; x++) {
+                double acc = 0.0;
+                for (int v = 0; v < N; v++)
+                    for (int u = 0; u < N; u++) {
+                        double F = (double)cm[d * 64 + v * 8 + u] * (double)q[v * 8 + u];
+                        double cu = u ? 1.0 : 1.0 / sqrt(2.0), cv = v ? 1.0 : 1.0 / sqrt(2.0);
+                        acc += cu * cv * F * cos((2 * x + 1) * u * ORC_PI / (2.0 * N)) *
+                               cos((2 * y + 1) * v * ORC_PI / (2.0 * N));
+                    }
+                samp[d][y * N + x] = 0.25 * acc;
+            }
+    }
+    for (int ty = 0; ty < ms; ty++)
+        for (int tx = 0; tx < ms; tx++) {
+            double Y, Cb, Cr;
+            if (j->sampling == 420) {
+                int du = (ty / N) * 2 + tx / N;
+                Y = samp[du][(ty % N) * N + tx % N];
+                Cb = samp[4][(ty / 2) * N + tx / 2];
+                Cr = samp[5][(ty / 2) * N + tx / 2];
+            } else {
+                Y = samp[0][ty * N + tx]; Cb = samp[1][ty * N + tx]; Cr = samp[2][ty * N + tx];
+            }
+            Y = clampd(Y + 128.0, 0.0, 255.0);
+            Cb = clampd(Cb + 128.0, 0.0, 255.0) - 128.0;
+            Cr = clampd(Cr + 128.0, 0.0, 255.0) - 128.0;
+            double rgbv[3] = {Y + 1.402 * Cr, Y - 0.344136 * Cb - 0.714136 * Cr, Y + 1.772 * Cb};
+            for (int c = 0; c < 3; c++) {
+                size_t o = ((size_t)ty * ms + tx) * 3 + c;
+                if (f64) f64[o] = rgbv[c];
+                if (rgb) rgb[o] = (uint8_t)clampd(floor(rgbv[c] + 0.5), 0.0, 255.0);
+            }
+        }
+}
+
+int orc_mcu_reduced(const orc_jpeg *j, const int16_t *coef_mcu, int scale_log2, uint8_t *out_rgb, double *out_f64) {
+    if (!j || !coef_mcu || scale_log2 < 0 || scale_log2 > 3) return ORC_E_ARG;
+    mcu_reduced(j, coef_mcu, scale_log2, out_rgb, out_f64);
+    return ORC_OK;
 }
 
 int orc_mcu_pixels(const orc_jpeg *j, const int16_t *coef_mcu, uint8_t *out_rgb, double *out_f64) {
@@ -485,12 +566,15 @@ static int axis(float u, int w, int linear, int64_t *x0, int64_t *x1, int *f) {
  * for an invalid pixel.  For trilinear, *tw = weight of the second level
  * in [0,256] and level_of_tap distinguishes the two levels. */
 static int pixel_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_count, const int32_t *lev_w,
-                      const int32_t *lev_h, const orc_gpixel *px, int filter, tap_t taps[8], int *lv0, int *lv1,
+                      const int32_t *lev_h, const orc_gpixel *px, int filter_flags, tap_t taps[8], int *lv0, int *lv1,
                       int *tw) {
+    const int filter = filter_flags & ORC_FILTER_MASK;
     if (px->tex >= (uint32_t)n_tex) return -1;
     if (!isfinite(px->u) || !isfinite(px->v) || !isfinite(px->lod)) return -1;
     int L = tex_count[px->tex], first = tex_first[px->tex];
     if (L <= 0) return -1;
+    /* without mip mapping every pixel samples level 0 */
+    if (filter_flags & ORC_NO_MIP) L = 1;
     int lv[2]; int lw[2]; int nl;
     if (filter == ORC_TRILINEAR) {
         float lod = px->lod;
@@ -523,6 +607,18 @@ static int pixel_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_co
         int64_t x0, x1, y0, y1; int fx, fy;
         int lin = filter != ORC_NEAREST;
         if (!axis(px->u, w, lin, &x0, &x1, &fx) || !axis(px->v, h, lin, &y0, &y1, &fy)) return -1;
+        if (filter == ORC_BILINEAR_CLAMPED) {
+            /* the paper's single-MCU variant: a tap outside the block of the
+             * texel under the sample point (the nearest filter's texel) reads
+             * that texel's row or column instead */
+            int64_t xc, yc, d0, d1; int f0;
+            axis(px->u, w, 0, &xc, &d0, &f0);
+            axis(px->v, h, 0, &yc, &d1, &f0);
+            if (x0 / 16 != xc / 16) x0 = xc;
+            if (x1 / 16 != xc / 16) x1 = xc;
+            if (y0 / 16 != yc / 16) y0 = yc;
+            if (y1 / 16 != yc / 16) y1 = yc;
+        }
         if (!lin) {
             taps[n++] = (tap_t){lev, x0, y0, 65536, lw[k]};
         } else {
@@ -542,6 +638,7 @@ static int pixel_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_co
 int64_t orc_mark(int n_tex, const int32_t *tex_first, const int32_t *tex_count, const int32_t *lev_w,
                  const int32_t *lev_h, const uint32_t *blk_base, const orc_gpixel *g, int64_t n_px, int filter,
                  uint8_t *vis) {
+    /* (filter: ORC_* mode, optionally with ORC_NO_MIP) */
     int64_t bad = 0;
     for (int64_t i = 0; i < n_px; i++) {
         if (g[i].tex == 0xFFFFFFFFu) continue;
@@ -572,7 +669,7 @@ int64_t orc_resolve(int n_tex, const int32_t *tex_first, const int32_t *tex_coun
         for (int k = 0; k < n; k++) {
             const uint8_t *img = level_rgb[taps[k].level];
             if (!img) { missing = 1; break; }
-            int side = (filter == ORC_TRILINEAR && taps[k].level != l0) ? 1 : 0;
+            int side = ((filter & ORC_FILTER_MASK) == ORC_TRILINEAR && taps[k].level != l0) ? 1 : 0;
             const uint8_t *t = img + ((size_t)taps[k].y * lev_w[taps[k].level] + (size_t)taps[k].x) * 3;
             for (int c = 0; c < 3; c++) acc[side][c] += (int64_t)t[c] * taps[k].w;
             if (frame_f64) {
@@ -588,7 +685,7 @@ int64_t orc_resolve(int n_tex, const int32_t *tex_first, const int32_t *tex_coun
         uint32_t rgb[3];
         for (int c = 0; c < 3; c++) {
             int64_t a = (acc[0][c] + 32768) >> 16;
-            if (filter == ORC_TRILINEAR && l1 != l0) {
+            if ((filter & ORC_FILTER_MASK) == ORC_TRILINEAR && l1 != l0) {
                 int64_t b = (acc[1][c] + 32768) >> 16;
                 /* a level whose weight is zero contributed no taps (acc = 0) */
                 a = (a * (256 - tw) + b * tw + 128) >> 8;

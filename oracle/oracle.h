@@ -72,6 +72,14 @@ int orc_decode_stripped_mcu(const orc_jpeg *j, const uint32_t *words, uint64_t n
                             const uint8_t *records, uint64_t n_records, uint32_t m, int16_t *out,
                             uint64_t *end_bit);
 
+/* The same for the library's predictor index (JPT_INDEX_PREDICTORS): the
+ * stream is the original segment, the record fields hold the DC predictors
+ * in force at each MCU; MCU `m` is decoded by the F.2 MCU body from its
+ * recorded start with those predictors. */
+int orc_decode_predicted_mcu(const orc_jpeg *j, const uint32_t *words, uint64_t n_words, uint64_t stream_bits,
+                             const uint8_t *records, uint64_t n_records, uint32_t m, int16_t *out,
+                             uint64_t *end_bit);
+
 /* fp64 inverse DCT of one 8x8 block by its definition:
  * s(x,y) = 1/4 sum_u sum_v C(u) C(v) F(v,u) cos((2x+1)u pi/16) cos((2y+1)v pi/16),
  * F natural order (index v*8+u, v vertical frequency), out index y*8+x. */
@@ -88,6 +96,15 @@ int orc_pixels(const orc_jpeg *j, const int16_t *coef, uint8_t *rgb, double *rgb
 /* The same for one MCU: out_rgb is the MCU's (16x16 or 8x8) texel tile,
  * row-major, 3 bytes per texel, including texels beyond the image border. */
 int orc_mcu_pixels(const orc_jpeg *j, const int16_t *coef_mcu, uint8_t *out_rgb, double *out_f64);
+
+/* Reduced-resolution texels of one MCU, scale 1/2^scale_log2 (0..3): each
+ * data unit's N x N samples (N = 8 >> scale_log2) by the N-point inverse
+ * DCT of its top-left N x N coefficients with the 8-point scaling (N = 1:
+ * the block mean), then +128, clamp, chroma replicated over 2x2 luma
+ * samples, colour with a single rounding.  out_rgb: the ((16 or 8) >>
+ * scale_log2) square tile, 3 bytes per texel; out_f64 (nullable) before
+ * rounding.  scale_log2 = 0 gives orc_mcu_pixels. */
+int orc_mcu_reduced(const orc_jpeg *j, const int16_t *coef_mcu, int scale_log2, uint8_t *out_rgb, double *out_f64);
 
 /* ---------------------------------------------------------- scenes ---- */
 /* A scene is a list of textures, each a chain of levels (level 0 first).
@@ -106,6 +123,16 @@ typedef struct { float u, v; uint32_t tex; float lod; } orc_gpixel;
 #define ORC_NEAREST 0
 #define ORC_BILINEAR 1
 #define ORC_TRILINEAR 2
+/* Bilinear weights, but a tap outside the 16x16 block of the texel under
+ * the sample point (the nearest filter's texel) takes that texel's column
+ * (or row) instead: the paper's resolve clamped to a single MCU (Linear
+ * Interpolation in the evaluation; Resolve).  The footprint, and so the
+ * marked set, is then that one block: the paper's centre-only marking. */
+#define ORC_BILINEAR_CLAMPED 3
+#define ORC_FILTER_MASK 0xFF
+/* OR'd into a filter: mip mapping off, every pixel samples level 0 (the
+ * "no mip" rows of the paper's performance table). */
+#define ORC_NO_MIP 0x100
 
 /* Mark (paper, Mark subsection, generalised to a filter footprint): for
  * every non-background pixel, set vis[block] = 1 for every block holding a
@@ -136,6 +163,54 @@ int64_t orc_resolve(int n_tex, const int32_t *tex_first, const int32_t *tex_coun
 int64_t orc_taps(int n_tex, const int32_t *tex_first, const int32_t *tex_count, const int32_t *lev_w,
                  const int32_t *lev_h, const orc_gpixel *g, int64_t n_px, int filter, int32_t *level, int32_t *x,
                  int32_t *y, double *w);
+
+/* ------------------------------------------------------ geometry ---- */
+/* A textured triangle (80 bytes) and a pinhole camera (64 bytes): the ray
+ * of pixel (x, y) of a W x H view leaves eye along
+ * fwd + sx right + sy up, sx = (2 (x + 0.5) / W - 1) tan_half_x,
+ * sy = (1 - 2 (y + 0.5) / H) tan_half_y. */
+typedef struct {
+    float p0[3], p1[3], p2[3];
+    float uv0[2], uv1[2], uv2[2];
+    uint32_t tex;
+    uint32_t reserved[4];
+} orc_triangle;
+typedef struct {
+    float eye[3], fwd[3], right[3], up[3];
+    float tan_half_x, tan_half_y;
+    float reserved[2];
+} orc_camera;
+
+/* Geometry pass (geometry.c), fp64: each pixel takes the nearest triangle
+ * (smallest t > 0; the lower index on equal t) whose closed area its centre
+ * ray hits; uv = the hit's barycentric blend of the vertices' uv; lod =
+ * log2 max(|(du, dv)_x|, |(du, dv)_y|) in texels of the texture's level 0
+ * (tex_w/tex_h), the differences taken to the rays one pixel right and one
+ * pixel down met with the same triangle's plane.  Pixels without a hit are
+ * background.  tri_out (nullable): the hit triangle per pixel (-1 none). */
+void orc_geometry(const orc_triangle *tris, int64_t n_tris, const orc_camera *cam, int W, int H,
+                  const int32_t *tex_w, const int32_t *tex_h, int n_tex, orc_gpixel *g, int32_t *tri_out);
+
+/* BC1 decoding by definition (bc1.c): blocks of a w x h image ->
+ * h x w x 3 bytes.  See bc1.c for the block layout and palette. */
+void orc_bc1_decode(const uint8_t *blocks, int w, int h, uint8_t *rgb);
+
+/* CPU on-demand baseline (ondemand.c): one frame of the paper's method on
+ * the host, on n_threads threads: mark (orc_mark over pixel ranges), list the
+ * marked blocks, decode only their MCUs by random access into the original
+ * segment (orc_decode_mcu_at from mcu_bit[L][m] with predictors
+ * pred[L][3m..3m+2], as recorded by orc_decode_seq) into level_rgb[L]
+ * (full-size level images; only the decoded blocks are written), then
+ * orc_resolve over pixel ranges.  vis: n_blocks bytes of scratch; list:
+ * n_blocks u32 of scratch.  times (nullable): seconds of mark, listing,
+ * decode, resolve.  Returns the number of invalid pixels plus MCUs that
+ * failed to decode, or -1 for bad arguments. */
+int64_t orc_ondemand_frame(int n_tex, const int32_t *tex_first, const int32_t *tex_count, int n_levels,
+                           const int32_t *lev_w, const int32_t *lev_h, const uint32_t *blk_base, uint64_t n_blocks,
+                           const orc_jpeg *const *jpegs, const uint64_t *const *mcu_bit, const int32_t *const *pred,
+                           uint8_t *const *level_rgb, const orc_gpixel *g, int64_t n_px, int filter,
+                           uint32_t *frame, uint8_t *vis, uint32_t *list, int n_threads, double times[4],
+                           uint64_t *n_decoded);
 
 #ifdef __cplusplus
 }

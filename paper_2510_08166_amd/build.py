@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libjpt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["host_index.cpp", "mark.hip", "decode.hip", "resolve.hip", "diff.hip", "graph.cpp"]
+SOURCES = ["host_index.cpp", "mark.hip", "decode.hip", "resolve.hip", "diff.hip", "graph.cpp", "geometry.hip", "bc1.hip",
+           "hashcache.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

@@ -8,11 +8,13 @@
 #include "jpt_internal.h"
 
 #define JPT_DEV __device__ __forceinline__
+#define JPT_DEV_HOST_INLINE __host__ __device__ __forceinline__
 
 // One level touched by a pixel: texel columns x0, x1 and rows y0, y1 with
 // fractional weights fx, fy in [0,256] (linear filters) and the level's weight
 // lw out of 256 (trilinear; 256 otherwise).  Taps of zero weight are skipped.
 struct LevelFoot {
+    uint32_t level;  // index into the scene's level array
     uint32_t blk_base, blk_cols;
     uint32_t x0, x1, y0, y1;
     uint32_t fx, fy;
@@ -114,18 +116,28 @@ JPT_DEV void load_desc_lds(const jpt_level_desc *__restrict__ levels, const jpt_
 }
 
 // Levels and footprints of a pixel (up to two levels).  Returns PIX_*.
+// Filter modes and flags of the C ABI, split.
+JPT_DEV_HOST_INLINE uint32_t filter_mode(uint32_t f) { return f & 0xFFu; }
+JPT_DEV_HOST_INLINE bool filter_no_mip(uint32_t f) { return (f & JPT_FILTER_MIP_OFF) != 0; }
+inline bool filter_valid(uint32_t f) { return filter_mode(f) <= JPT_FILTER_BILINEAR_CLAMPED && (f & ~0x1FFu) == 0; }
+
 // Branch-free over the lanes of a wave: every lane computes with clamped
 // descriptor indices and the checks only pick the status at the end.
+// `filter` is a JPT_FILTER_* mode; with no_mip every pixel samples level 0
+// (JPT_FILTER_MIP_OFF).  JPT_FILTER_BILINEAR_CLAMPED takes the bilinear
+// taps and moves a tap that lies outside the 16x16 block of the texel under
+// the sample point (the nearest filter's texel) onto that texel's column or
+// row, so that every tap, and the footprint, is that one block.
 template <class Desc>
 JPT_DEV int pixel_footprint(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter, LevelFoot foot[2],
-                            int &nfoot, uint32_t &tw) {
+                            int &nfoot, uint32_t &tw, bool no_mip = false) {
     nfoot = 0;
     tw = 0;
     const bool bg = px.tex == JPT_TEX_BACKGROUND;
     if (n_tex == 0) return bg ? PIX_BACKGROUND : PIX_INVALID;  // (uniform)
     bool ok = px.tex < n_tex && isfinite(px.u) && isfinite(px.v) && isfinite(px.lod);
     const TexRec td = D.tex(px.tex < n_tex ? px.tex : 0u);
-    const int L = (int)td.n;
+    const int L = no_mip && td.n > 0 ? 1 : (int)td.n;
     ok = ok && L > 0;
     int lv0, nl;
     uint32_t lw0, lw1 = 0;
@@ -157,11 +169,21 @@ JPT_DEV int pixel_footprint(const Desc &D, uint32_t n_tex, const jpt_gpixel &px,
         // (a second level exists only when lv0 + 1 <= L - 1)
         const uint32_t li = ok ? td.first + (uint32_t)(k == 0 ? lv0 : min(lv0 + 1, L - 1)) : 0u;
         const LevRec lr = D.lev(li);
+        F.level = li;
         F.blk_base = lr.blk_base;
         F.blk_cols = lr.blk_cols;
         F.lw = k == 0 ? lw0 : lw1;
         const bool ax = axis(px.u, lr.w, linear, F.x0, F.x1, F.fx);
         const bool ay = axis(px.v, lr.h, linear, F.y0, F.y1, F.fy);
+        if (filter == JPT_FILTER_BILINEAR_CLAMPED) {
+            uint32_t xc, yc, d0, d1, f0;
+            axis(px.u, lr.w, false, xc, d0, f0);
+            axis(px.v, lr.h, false, yc, d1, f0);
+            F.x0 = (F.x0 >> 4) == (xc >> 4) ? F.x0 : xc;
+            F.x1 = (F.x1 >> 4) == (xc >> 4) ? F.x1 : xc;
+            F.y0 = (F.y0 >> 4) == (yc >> 4) ? F.y0 : yc;
+            F.y1 = (F.y1 >> 4) == (yc >> 4) ? F.y1 : yc;
+        }
         if (k < nl) ok = ok && ax && ay;
     }
     if (bg) return PIX_BACKGROUND;

@@ -7,22 +7,35 @@
 //   jpt_dequantize   F = coef * Q, natural order (the leaf of the form)
 //   jpt_fwd_float    F -> float texels -> float frame
 //   jpt_backward     dL/dframe -> dL/dtexel (resolve adjoint, deterministic
-//                    fixed-point atomics) -> colour adjoint, 2x2 chroma sum
-//                    -> transposed IDCT -> dL/dF
+//                    fixed-point atomics in a unit set by max |dL/dframe|)
+//                    -> colour adjoint, 2x2 chroma sum -> transposed IDCT
+//                    -> dL/dF
 //
 // The 8x8 transforms are separable fp32 products with the 1-D basis
 // P[u][x] = C(u)/2 cos((2x+1) u pi / 16) held in LDS.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "dev_common.h"
 
 namespace {
 
 constexpr int kItemCoefs = JPT_ITEMS_DU * 64;
-// dL/dtexel accumulates in 64-bit fixed point with this many fraction bits,
-// so that the sum does not depend on the order of the atomics
-constexpr float kFixScale = 4294967296.0f;  // 2^32
-constexpr float kFixInv = 1.0f / 4294967296.0f;
+// dL/dtexel accumulates in 64-bit fixed point, so that the sum does not
+// depend on the order of the atomics.  The unit is 2^-shift with shift
+// chosen per call from m = max |dL/dframe|: every tap product g w (w <= 1)
+// is below 2^kFixBits units, so a texel's sum stays exact for up to
+// 2^(63 - kFixBits) taps, and each product is rounded to m 2^-(kFixBits+1)
+// or better, whatever the scale of the loss.
+constexpr int kFixBits = 36;
+
+// The unit exponent for a largest |dL/dframe| whose fp32 bits are mbits
+// (m < 2^e with e from the biased exponent; m = 0 gives the smallest e).
+__device__ __forceinline__ int fix_shift(uint32_t mbits) {
+    const int e = (int)((mbits >> 23) & 255u) - 126;
+    return kFixBits - e;
+}
 
 struct ZigZagD {
     uint8_t nat[64];
@@ -167,14 +180,15 @@ struct FTaps {
 };
 
 template <class Desc>
-__device__ __forceinline__ int float_taps(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter,
+__device__ __forceinline__ int float_taps(const Desc &D, uint32_t n_tex, const jpt_gpixel &px, uint32_t filter_flags,
                                           const uint32_t *__restrict__ slot_of, FTaps &T) {
 #pragma unroll
     for (int k = 0; k < 8; k++) { T.slot[k] = 0; T.off[k] = 0; T.w[k] = 0.0f; }
     LevelFoot foot[2];
     int nf;
     uint32_t tw;
-    const int st = pixel_footprint(D, n_tex, px, filter, foot, nf, tw);
+    const uint32_t filter = filter_mode(filter_flags);
+    const int st = pixel_footprint(D, n_tex, px, filter, foot, nf, tw, filter_no_mip(filter_flags));
     if (st != PIX_VALID) return st;
 #pragma unroll
     for (int k = 0; k < 2; k++) {
@@ -274,7 +288,8 @@ __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__res
                                                      uint32_t H, uint32_t pitch, uint32_t filter,
                                                      const uint32_t *__restrict__ slot_of,
                                                      const float *__restrict__ dframe,
-                                                     unsigned long long *__restrict__ dtexel) {
+                                                     unsigned long long *__restrict__ dtexel,
+                                                     const uint32_t *__restrict__ counters) {
     __shared__ TexRec s_t[kLdsDesc ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kLdsDesc ? kLdsLevCap : 1];
     __shared__ uint32_t s_key[kAccSize];
@@ -283,6 +298,7 @@ __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__res
     for (int i = threadIdx.x; i < kAccSize; i += 256) s_key[i] = 0xFFFFFFFFu;
     for (int i = threadIdx.x; i < 3 * kAccSize; i += 256) s_val[i] = 0ull;
     __syncthreads();
+    const int shift = fix_shift(counters[JPT_CTR_GRAD_MAX]);
     const uint32_t x = blockIdx.x * 64 + (threadIdx.x & 63);
     for (int r = 0; r < kBwdRows; r++) {
         const uint32_t y = blockIdx.y * (4 * kBwdRows) + r * 4 + (threadIdx.x >> 6);
@@ -298,8 +314,8 @@ __global__ __launch_bounds__(256) void k_bwd_resolve(const jpt_level_desc *__res
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (T.w[k] == 0.0f || T.slot[k] == JPT_SLOT_NONE) continue;
-            acc_add(s_key, s_val, dtexel, T.slot[k] * 256u + T.off[k], __float2ll_rn(g0 * T.w[k] * kFixScale),
-                    __float2ll_rn(g1 * T.w[k] * kFixScale), __float2ll_rn(g2 * T.w[k] * kFixScale));
+            acc_add(s_key, s_val, dtexel, T.slot[k] * 256u + T.off[k], __float2ll_rn(ldexpf(g0 * T.w[k], shift)),
+                    __float2ll_rn(ldexpf(g1 * T.w[k], shift)), __float2ll_rn(ldexpf(g2 * T.w[k], shift)));
         }
     }
     __syncthreads();
@@ -321,6 +337,7 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
                                                    const uint32_t *__restrict__ slot_of,
                                                    const unsigned long long *__restrict__ dtexel,
                                                    float *__restrict__ dF, uint32_t max_items) {
+    const int shift = fix_shift(counters[JPT_CTR_GRAD_MAX]);
     __shared__ float s_P[64];
     __shared__ float s_dS[kItemCoefs];  // dL/d(sample) per data unit, pixel order
     __shared__ float s_R[64];
@@ -342,8 +359,8 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
             if (!g.s444) { ty = 2 * r + (k >> 1); tx = 2 * c + (k & 1); }
             else { ty = 8 * (g.q >> 1) + r; tx = 8 * (g.q & 1) + c; }
             const unsigned long long *d = src + (ty * 16 + tx) * 3;
-            const float dR = (float)(long long)d[0] * kFixInv, dG = (float)(long long)d[1] * kFixInv,
-                        dB = (float)(long long)d[2] * kFixInv;
+            const float dR = ldexpf((float)(long long)d[0], -shift), dG = ldexpf((float)(long long)d[1], -shift),
+                        dB = ldexpf((float)(long long)d[2], -shift);
             // adjoint of R = Y + 1.402 Cr, G = Y - .344136 Cb - .714136 Cr, B = Y + 1.772 Cb
             const float dY = dR + dG + dB;
             sCb += -0.344136f * dG + 1.772f * dB;  // a chroma sample feeds its whole 2x2 square
@@ -373,15 +390,37 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
     }
 }
 
+// The largest |dL/dframe| of one view (fp32 bits; non-negative floats order
+// as their bits), max-reduced into counters[JPT_CTR_GRAD_MAX]; a non-finite
+// entry raises JPT_ERR_GRAD.
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, uint64_t n,
+                                                uint32_t *__restrict__ counters) {
+    uint32_t m = 0;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const float v = fabsf(g[i]);
+        bad |= !(v <= 3.4028234664e38f);
+        m = max(m, __float_as_uint(v));
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_GRAD);
+        if (m) atomicMax(counters + JPT_CTR_GRAD_MAX, bad ? 0u : m);
+    }
+}
+
 // Clear the texel adjoints of the listed items' slots (a block's 16 x 16 x 3
-// entries once: by its 4:2:0 item, or by quadrant 0 of a 4:4:4 block).
+// entries once: by its 4:2:0 item, or by quadrant 0 of a 4:4:4 block), and
+// the largest-gradient counter.
 __global__ __launch_bounds__(256) void k_zero_items(const jpt_level_desc *__restrict__ levels,
                                                     const uint32_t *__restrict__ word_level,
                                                     const uint32_t *__restrict__ work,
-                                                    const uint32_t *__restrict__ counters,
+                                                    uint32_t *__restrict__ counters,
                                                     const uint32_t *__restrict__ slot_of,
                                                     unsigned long long *__restrict__ dtexel, uint32_t max_items) {
     const uint32_t n_items = min(counters[JPT_CTR_ITEMS], max_items);
+    if (blockIdx.x == 0 && threadIdx.x == 0) counters[JPT_CTR_GRAD_MAX] = 0;
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const uint32_t w = work[it];
         const uint32_t b = (w & 0x7FFFFFFFu) >> 2, q = w & 3u;
@@ -397,7 +436,7 @@ bool desc_fits(const jpt_scene *s) { return s->n_textures <= kLdsTexCap && s->n_
 
 jpt_status check(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                  const jpt_frame *frame, const jpt_cache *cache) {
-    if (!scene || !frame || !cache || (n_views && !views) || filter > JPT_FILTER_TRILINEAR) return JPT_E_ARG;
+    if (!scene || !frame || !cache || (n_views && !views) || !filter_valid(filter)) return JPT_E_ARG;
     if (!scene->levels || !scene->textures || !scene->word_level || !frame->work || !frame->counters ||
         !cache->slot_of)
         return JPT_E_ARG;
@@ -461,6 +500,12 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
     hipLaunchKernelGGL(k_zero_items, dim3(2048), dim3(256), 0, st, scene->levels, scene->word_level, frame->work,
                        frame->counters, cache->slot_of, dt, row_limit(frame, n_rows));
     HIP_CHECK_LAUNCH();
+    size_t total = 0;
+    for (uint32_t v = 0; v < n_views; v++) total += (size_t)views[v].width * views[v].height * 3;
+    if (total)
+        hipLaunchKernelGGL(k_absmax, dim3((uint32_t)std::min<size_t>((total + 255) / 256, 2048)), dim3(256), 0, st,
+                           dframe, (uint64_t)total, frame->counters);
+    HIP_CHECK_LAUNCH();
     size_t off = 0;
     for (uint32_t v = 0; v < n_views; v++) {
         const jpt_view &V = views[v];
@@ -469,11 +514,11 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
         if (desc_fits(scene))
             hipLaunchKernelGGL(k_bwd_resolve<true>, grid, dim3(256), 0, st, scene->levels, scene->textures,
                                scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
-                               cache->slot_of, dframe + off, dt);
+                               cache->slot_of, dframe + off, dt, frame->counters);
         else
             hipLaunchKernelGGL(k_bwd_resolve<false>, grid, dim3(256), 0, st, scene->levels, scene->textures,
                                scene->n_textures, scene->n_levels, V.gbuf, V.width, V.height, V.pitch, filter,
-                               cache->slot_of, dframe + off, dt);
+                               cache->slot_of, dframe + off, dt, frame->counters);
         HIP_CHECK_LAUNCH();
         off += (size_t)V.width * V.height * 3;
     }

@@ -11,6 +11,9 @@
 // The argument structs keep fixed sizes (bindings mirror them field by field).
 static_assert(sizeof(jpt_level_desc) == 64 && sizeof(jpt_texture_desc) == 16, "descriptor layout");
 static_assert(sizeof(jpt_scene) == 64 && sizeof(jpt_view) == 32 && sizeof(jpt_frame) == 48, "argument layout");
+static_assert(sizeof(jpt_triangle) == 80 && sizeof(jpt_camera) == 64, "geometry layout");
+static_assert(sizeof(jpt_cache) == 88 && sizeof(jpt_level_info) == 1464, "cache and level info layout");
+static_assert(sizeof(jpt_bc1_level) == 24 && sizeof(jpt_bc1_scene) == 24, "BC1 layout");
 
 namespace {
 
@@ -227,7 +230,15 @@ void copy_bits(WordWriter &out, const uint8_t *src, uint64_t src_nbits, uint64_t
 // ======================================================================
 extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level_info *info, uint32_t *stream_out,
                                       size_t stream_cap_words, uint8_t *records_out, size_t records_cap_bytes) {
-    if (!jpeg || !info) return JPT_E_ARG;
+    return jpt_build_index_ex(jpeg, len, JPT_INDEX_SPLICED, info, stream_out, stream_cap_words, records_out,
+                              records_cap_bytes);
+}
+
+extern "C" jpt_status jpt_build_index_ex(const uint8_t *jpeg, size_t len, uint32_t kind, jpt_level_info *info,
+                                         uint32_t *stream_out, size_t stream_cap_words, uint8_t *records_out,
+                                         size_t records_cap_bytes) {
+    if (!jpeg || !info || kind > JPT_INDEX_PREDICTORS) return JPT_E_ARG;
+    const bool spliced = kind == JPT_INDEX_SPLICED;
     Parsed P;
     jpt_status st = parse(jpeg, len, P);
     if (st != JPT_OK) return st;
@@ -276,6 +287,8 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
     uint64_t removed = 0;
     for (uint32_t m = 0; m < I.n_mcu; m++) {
         start[m] = ww.nbits + (br.pos - copied_from);
+        if (!spliced)  // the predictors in force when the MCU starts
+            for (int c = 0; c < 3; c++) dcs[(size_t)m * 3 + c] = pred[c];
         for (int d = 0; d < ndu; d++) {
             int c = P.sampling == 420 ? (d < 4 ? 0 : d - 3) : d;
             int tsel = c ? 1 : 0;
@@ -293,7 +306,7 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
             // records store the absolute ones in 12 bits, and the decoders'
             // arithmetic assumes it of the differential ones too
             if (pred[c] < -2048 || pred[c] > 2047) return JPT_E_RANGE;
-            if (absolute) {
+            if (absolute && spliced) {
                 dcs[(size_t)m * 3 + c] = pred[c];
                 // splice: copy the pending original bits, skip this DC code
                 copy_bits(ww, P.ecs.data(), ecs_bits, copied_from, dc_from - copied_from);
@@ -335,6 +348,7 @@ extern "C" jpt_status jpt_build_index(const uint8_t *jpeg, size_t len, jpt_level
         for (uint32_t i = 1; i < 9 && 9 * g + i < I.n_mcu; i++)
             if (start[9 * g + i] - start[9 * g] > 0xFFFF) return JPT_E_RANGE;
 
+    I.index_kind = (uint16_t)kind;
     I.index_bits_per_mcu = (32.0 + 16.0 * 8.0) / 9.0;
     I.dc_bits_per_mcu = 36.0;
     const double mcu_px = (double)ms * ms;
@@ -482,7 +496,8 @@ extern "C" jpt_status jpt_make_level_desc(const jpt_level_info *info, uint64_t s
     std::memset(out, 0, sizeof *out);
     out->stream = stream_dptr;
     out->records = records_dptr;
-    out->stream_bits = info->stream_bits;
+    out->stream_bits = (uint32_t)info->stream_bits;
+    out->index_kind = info->index_kind;
     out->width = info->width;
     out->height = info->height;
     out->blk_cols = info->blk_cols;

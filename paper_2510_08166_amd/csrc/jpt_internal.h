@@ -53,6 +53,8 @@
 #define JPT_META_R0 9
 #define JPT_META_D1 10        // chosen digit 1, and evictions left below it
 #define JPT_META_R1 11
+#define JPT_META_QCOUNT 12    // hash-map cache: blocks queued this frame
+#define JPT_META_VISIBLE 13   // hash-map cache: blocks read this frame
 #define JPT_META_HIST 16      // JPT_LRU_MAX_AGE + 1 bins
 #define JPT_META_DH0 (JPT_META_HIST + JPT_LRU_MAX_AGE + 1)  // 2048 bins
 #define JPT_META_DH1 (JPT_META_DH0 + 2048)                  // 2048 bins

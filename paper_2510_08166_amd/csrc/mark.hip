@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
+#include "hashcache.h"
 
 namespace {
 
@@ -160,9 +161,9 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                        uint32_t n_lev, const ViewTable tab,
                                                        uint32_t *__restrict__ vis, const TileCounts tc,
-                                                       uint32_t *__restrict__ err_word) {
+                                                       uint32_t *__restrict__ err_word, bool no_mip) {
     constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
-    constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
+    constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize], s_ctile[kCntSlots];
     __shared__ unsigned long long s_cval[kCntSlots];
     __shared__ TexRec s_t[kDesc != DESC_HBM ? kLdsTexCap : 1];
@@ -205,10 +206,11 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
             int nf;
             uint32_t tw;
             int st;
-            if constexpr (kDesc == DESC_LDS) st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px, kFilter, foot, nf, tw);
+            if constexpr (kDesc == DESC_LDS)
+                st = pixel_footprint(LdsDesc{s_t, s_l}, n_tex, px, kFilter, foot, nf, tw, no_mip);
             else if constexpr (kDesc == DESC_TEX_LDS)
-                st = pixel_footprint(MixDesc{s_t, levels}, n_tex, px, kFilter, foot, nf, tw);
-            else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw);
+                st = pixel_footprint(MixDesc{s_t, levels}, n_tex, px, kFilter, foot, nf, tw, no_mip);
+            else st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw, no_mip);
             if (st == PIX_INVALID) {
                 invalid = true;
             } else if (st == PIX_VALID) {
@@ -266,18 +268,20 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
 
 template <uint32_t kFilter, int kDesc>
 void launch_mark_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
-                      const TileCounts &tc, uint32_t *err_word, hipStream_t st) {
+                      const TileCounts &tc, uint32_t *err_word, bool no_mip, hipStream_t st) {
     hipLaunchKernelGGL((k_mark<kFilter, kDesc>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                       scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word);
+                       scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word, no_mip);
 }
 
 template <uint32_t kFilter>
 void launch_mark(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
-                 const TileCounts &tc, uint32_t *err_word, hipStream_t st) {
+                 const TileCounts &tc, uint32_t *err_word, bool no_mip, hipStream_t st) {
     switch (desc_mode(scene->n_textures, scene->n_levels)) {
-    case DESC_LDS: launch_mark_desc<kFilter, DESC_LDS>(scene, tab, groups, frame, tc, err_word, st); break;
-    case DESC_TEX_LDS: launch_mark_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, frame, tc, err_word, st); break;
-    default: launch_mark_desc<kFilter, DESC_HBM>(scene, tab, groups, frame, tc, err_word, st); break;
+    case DESC_LDS: launch_mark_desc<kFilter, DESC_LDS>(scene, tab, groups, frame, tc, err_word, no_mip, st); break;
+    case DESC_TEX_LDS:
+        launch_mark_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, frame, tc, err_word, no_mip, st);
+        break;
+    default: launch_mark_desc<kFilter, DESC_HBM>(scene, tab, groups, frame, tc, err_word, no_mip, st); break;
     }
 }
 
@@ -598,7 +602,8 @@ __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ o
                                                   const uint32_t *__restrict__ last_used,
                                                   const uint32_t *__restrict__ vis, uint32_t n_slots,
                                                   uint32_t frame_no, uint32_t *__restrict__ meta,
-                                                  const uint64_t *__restrict__ grp, uint32_t n_grp) {
+                                                  const uint64_t *__restrict__ grp, uint32_t n_grp,
+                                                  uint32_t evict_all) {
     __shared__ uint32_t s_h[kAgeBins];
     __shared__ uint32_t s_d[kDigitBins];
     __shared__ uint32_t s_need;
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(256) void k_lru_hist(const uint32_t *__restrict__ o
         }
     }
     __syncthreads();
-    if (s_need == 0) return;
+    if (s_need == 0 || evict_all) return;  // (evicting every candidate needs no ranking)
     const uint32_t f = lru_frame(frame_no, meta);
     for (int k = threadIdx.x; k < kAgeBins; k += 256) s_h[k] = 0;
     for (int k = threadIdx.x; k < kDigitBins; k += 256) s_d[k] = 0;
@@ -697,9 +702,18 @@ __global__ __launch_bounds__(256) void k_lru_evict(uint32_t *__restrict__ owner,
                                                    uint32_t frame_no, uint32_t *__restrict__ slot_of,
                                                    uint32_t *__restrict__ resident, uint32_t *__restrict__ free_stack,
                                                    uint32_t *__restrict__ tie_mask, uint32_t *__restrict__ meta,
-                                                   uint32_t *__restrict__ counters) {
+                                                   uint32_t *__restrict__ counters, uint32_t evict_all) {
     __shared__ uint32_t s_d[kDigitBins];
     const uint32_t need = meta[JPT_META_NEED];
+    if (evict_all) {
+        // the paper's policy: every resident block this frame does not read goes
+        if (blockIdx.x == 0 && threadIdx.x == 0) meta[JPT_META_TIES] = 0xFFFFFFFFu;
+        for (uint32_t s = blockIdx.x * 256 + threadIdx.x; s < n_slots; s += gridDim.x * 256) {
+            const uint32_t b = owner[s];
+            if (b != JPT_SLOT_NONE && !bit_set(vis, b)) evict(s, b, owner, slot_of, resident, free_stack, meta);
+        }
+        return;
+    }
     if (need == 0) return;
     uint32_t abin, ties;
     select_bin<kAgeBins>(meta + JPT_META_HIST, need, abin, ties);
@@ -878,6 +892,7 @@ uint32_t grid_for(uint64_t n, uint32_t per_group, uint32_t cap) {
 }
 
 bool lru_ok(const jpt_cache *c) {
+    // (the LRU and evict-invisible policies keep the same per-slot state)
     return c->texels && c->slot_of && c->owner && c->last_used && c->resident && c->free_stack && c->meta &&
            c->tie_mask && c->n_slots > 0;
 }
@@ -885,7 +900,10 @@ bool lru_ok(const jpt_cache *c) {
 }  // namespace
 
 extern "C" jpt_status jpt_cache_reset(const jpt_scene *scene, jpt_cache *cache, void *stream) {
-    if (!scene || !cache || cache->policy != JPT_CACHE_LRU || !lru_ok(cache) || scene->n_blocks == 0 ||
+    if (scene && cache && cache->policy == JPT_CACHE_HASH)
+        return hash_cache_ok(cache) ? hash_cache_reset(cache, (hipStream_t)stream) : JPT_E_ARG;
+    if (!scene || !cache || (cache->policy != JPT_CACHE_LRU && cache->policy != JPT_CACHE_EVICT_INVISIBLE) ||
+        !lru_ok(cache) || scene->n_blocks == 0 ||
         (scene->n_blocks & 31))
         return JPT_E_ARG;
     const uint32_t n_words = scene->n_blocks / 32;
@@ -904,7 +922,7 @@ namespace {
 jpt_status mark_args(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                      const jpt_frame *frame) {
     if (!scene || !frame || (n_views && !views)) return JPT_E_ARG;
-    if (filter > JPT_FILTER_TRILINEAR) return JPT_E_ARG;
+    if (!filter_valid(filter)) return JPT_E_ARG;
     if (!scene->levels || !scene->textures || !scene->word_level || scene->n_blocks == 0 ||
         (scene->n_blocks & 31) || scene->n_blocks > (1u << 29))
         return JPT_E_ARG;
@@ -929,8 +947,16 @@ namespace {
 
 jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                       jpt_frame *frame, uint64_t *scan, jpt_cache *cache, const jpt_tuning *tuning, void *stream) {
-    const bool lru = cache && cache->policy == JPT_CACHE_LRU;
-    if (cache && cache->policy > JPT_CACHE_LRU) return JPT_E_ARG;
+    if (cache && cache->policy == JPT_CACHE_HASH) {
+        if (!hash_cache_ok(cache)) return JPT_E_ARG;
+        for (uint32_t v = 0; v < n_views; v++)
+            if (!views[v].gbuf || views[v].pitch < views[v].width) return JPT_E_ARG;
+        return hash_mark_frame(scene, views, n_views, filter, frame, cache, (hipStream_t)stream);
+    }
+    // both cache policies with resident state run the cache-update kernels
+    const bool lru = cache && (cache->policy == JPT_CACHE_LRU || cache->policy == JPT_CACHE_EVICT_INVISIBLE);
+    const uint32_t evict_all = cache && cache->policy == JPT_CACHE_EVICT_INVISIBLE ? 1u : 0u;
+    if (cache && cache->policy > JPT_CACHE_EVICT_INVISIBLE) return JPT_E_ARG;
     if (lru && !lru_ok(cache)) return JPT_E_ARG;
     for (uint32_t v = 0; v < n_views; v++)
         if (!views[v].gbuf || views[v].pitch < views[v].width) return JPT_E_ARG;
@@ -966,10 +992,15 @@ jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_
         uint32_t groups = tab.span;
         if (tuning && tuning->mark_groups && tuning->mark_groups < groups)
             groups = xcd ? (tuning->mark_groups + 7) / 8 * 8 : tuning->mark_groups;
-        if (filter == JPT_FILTER_NEAREST) launch_mark<JPT_FILTER_NEAREST>(scene, tab, groups, frame, tc, err_word, st);
-        else if (filter == JPT_FILTER_BILINEAR)
-            launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, tc, err_word, st);
-        else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, tc, err_word, st);
+        const uint32_t mode = filter_mode(filter);
+        const bool no_mip = filter_no_mip(filter);
+        if (mode == JPT_FILTER_NEAREST)
+            launch_mark<JPT_FILTER_NEAREST>(scene, tab, groups, frame, tc, err_word, no_mip, st);
+        else if (mode == JPT_FILTER_BILINEAR)
+            launch_mark<JPT_FILTER_BILINEAR>(scene, tab, groups, frame, tc, err_word, no_mip, st);
+        else if (mode == JPT_FILTER_BILINEAR_CLAMPED)
+            launch_mark<JPT_FILTER_BILINEAR_CLAMPED>(scene, tab, groups, frame, tc, err_word, no_mip, st);
+        else launch_mark<JPT_FILTER_TRILINEAR>(scene, tab, groups, frame, tc, err_word, no_mip, st);
         HIP_CHECK_LAUNCH();
     }
     if (!lru) {
@@ -989,10 +1020,10 @@ jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_
     HIP_CHECK_LAUNCH();
     const uint32_t sg = grid_for(cache->n_slots, 256, 2048);
     hipLaunchKernelGGL(k_lru_hist, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                       cache->n_slots, f, cache->meta, grp, n_grp);
+                       cache->n_slots, f, cache->meta, grp, n_grp, evict_all);
     hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
-                       cache->meta, frame->counters);
+                       cache->meta, frame->counters, evict_all);
     const uint32_t dg = grid_for(cache->n_slots, 256, 512);
     hipLaunchKernelGGL(k_lru_deep1, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->meta);

@@ -1,7 +1,8 @@
 // Resolve (paper: Method, "Resolve"): each pixel fetches its filter taps from
 // the cache slots of their blocks and blends them with integer weights.
 // Every tap a pixel reads was marked, so no clamping at undecoded MCU borders
-// is needed (the footprint marking makes the result exact).
+// is needed (the footprint marking makes the result exact); the paper's
+// variant clamped to one MCU is the filter JPT_FILTER_BILINEAR_CLAMPED.
 //
 // A workgroup shades 64 x 16 pixel tiles, 4 rows per lane, walking the
 // tiles of every view in the launch's table with a stride of gridDim.x.  The scene's
@@ -11,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
+#include "hashcache.h"
 
 namespace {
 
@@ -20,7 +22,7 @@ constexpr int kRows = kTileH / (kThreads / 64);
 
 template <uint32_t kFilter>
 struct FilterTraits {
-    static constexpr int kTaps = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_BILINEAR ? 4 : 8);
+    static constexpr int kTaps = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
 };
 
 // Taps of one pixel: block id, texel offset inside the block's slot and
@@ -32,12 +34,13 @@ struct Taps {
 
 template <uint32_t kFilter, class Desc>
 __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const jpt_gpixel &px,
-                                          Taps<FilterTraits<kFilter>::kTaps> &T, uint32_t &tw, int &nf) {
+                                          Taps<FilterTraits<kFilter>::kTaps> &T, uint32_t &tw, int &nf,
+                                          bool no_mip) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
 #pragma unroll
     for (int t = 0; t < kTaps; t++) { T.blk[t] = 0; T.off[t] = 0; T.w[t] = 0; }
     LevelFoot foot[2];
-    const int st = pixel_footprint(D, n_tex, px, kFilter, foot, nf, tw);
+    const int st = pixel_footprint(D, n_tex, px, kFilter, foot, nf, tw, no_mip);
     if (st != PIX_VALID) return st;
 #pragma unroll
     for (int k = 0; k < 2; k++) {
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
                                                       const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                       uint32_t n_lev, const ViewTable tab,
                                                       const uint32_t *__restrict__ slot_of,
-                                                      const uint32_t *__restrict__ texels) {
+                                                      const uint32_t *__restrict__ texels, bool no_mip) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
     __shared__ TexRec s_t[kDesc != DESC_HBM ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kDesc == DESC_LDS ? kLdsLevCap : 1];
@@ -100,10 +103,11 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
             Taps<kTaps> T;
             uint32_t tw;
             int nf, st;
-            if constexpr (kDesc == DESC_LDS) st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf);
+            if constexpr (kDesc == DESC_LDS)
+                st = pixel_taps<kFilter>(LdsDesc{s_t, s_l}, n_tex, px[r], T, tw, nf, no_mip);
             else if constexpr (kDesc == DESC_TEX_LDS)
-                st = pixel_taps<kFilter>(MixDesc{s_t, levels}, n_tex, px[r], T, tw, nf);
-            else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf);
+                st = pixel_taps<kFilter>(MixDesc{s_t, levels}, n_tex, px[r], T, tw, nf, no_mip);
+            else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf, no_mip);
             // all slot lookups of the pixel, then all texel loads
             // unused taps read block 0 / slot 0 (valid addresses) and get weight 0
             uint32_t slot[kTaps], tex[kTaps];
@@ -159,17 +163,19 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
 
 template <uint32_t kFilter, int kDesc>
 void launch_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache,
-                 hipStream_t st) {
+                 bool no_mip, hipStream_t st) {
     hipLaunchKernelGGL((k_resolve<kFilter, kDesc>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
-                       scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels);
+                       scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels,
+                       no_mip);
 }
 
 template <uint32_t kFilter>
-void launch(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache, hipStream_t st) {
+void launch(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache, bool no_mip,
+            hipStream_t st) {
     switch (desc_mode(scene->n_textures, scene->n_levels)) {
-    case DESC_LDS: launch_desc<kFilter, DESC_LDS>(scene, tab, groups, cache, st); break;
-    case DESC_TEX_LDS: launch_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, cache, st); break;
-    default: launch_desc<kFilter, DESC_HBM>(scene, tab, groups, cache, st); break;
+    case DESC_LDS: launch_desc<kFilter, DESC_LDS>(scene, tab, groups, cache, no_mip, st); break;
+    case DESC_TEX_LDS: launch_desc<kFilter, DESC_TEX_LDS>(scene, tab, groups, cache, no_mip, st); break;
+    default: launch_desc<kFilter, DESC_HBM>(scene, tab, groups, cache, no_mip, st); break;
     }
 }
 
@@ -181,12 +187,16 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
     (void)frame;
     if (!scene || (n_views && !views) || !cache || !cache->slot_of || !cache->texels || cache->n_slots == 0)
         return JPT_E_ARG;
-    if (filter > JPT_FILTER_TRILINEAR || !scene->levels || !scene->textures) return JPT_E_ARG;
+    if (!filter_valid(filter) || !scene->levels || !scene->textures) return JPT_E_ARG;
+    const uint32_t mode = filter_mode(filter);
+    const bool no_mip = filter_no_mip(filter);
     for (uint32_t v = 0; v < n_views; v++)
         if (!views[v].gbuf || !views[v].frame || views[v].pitch < views[v].width ||
             views[v].frame_pitch < views[v].width)
             return JPT_E_ARG;
     hipStream_t st = (hipStream_t)stream;
+    if (cache->policy == JPT_CACHE_HASH)
+        return hash_cache_ok(cache) ? hash_resolve(scene, views, n_views, filter, cache, st) : JPT_E_ARG;
     const bool xcd = tuning && (tuning->flags & JPT_TUNE_XCD_TILES);
     for (uint32_t v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
         ViewTable tab;
@@ -196,9 +206,11 @@ extern "C" jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views,
         uint32_t groups = tab.span;
         if (tuning && tuning->resolve_groups && tuning->resolve_groups < groups)
             groups = xcd ? (tuning->resolve_groups + 7) / 8 * 8 : tuning->resolve_groups;
-        if (filter == JPT_FILTER_NEAREST) launch<JPT_FILTER_NEAREST>(scene, tab, groups, cache, st);
-        else if (filter == JPT_FILTER_BILINEAR) launch<JPT_FILTER_BILINEAR>(scene, tab, groups, cache, st);
-        else launch<JPT_FILTER_TRILINEAR>(scene, tab, groups, cache, st);
+        if (mode == JPT_FILTER_NEAREST) launch<JPT_FILTER_NEAREST>(scene, tab, groups, cache, no_mip, st);
+        else if (mode == JPT_FILTER_BILINEAR) launch<JPT_FILTER_BILINEAR>(scene, tab, groups, cache, no_mip, st);
+        else if (mode == JPT_FILTER_BILINEAR_CLAMPED)
+            launch<JPT_FILTER_BILINEAR_CLAMPED>(scene, tab, groups, cache, no_mip, st);
+        else launch<JPT_FILTER_TRILINEAR>(scene, tab, groups, cache, no_mip, st);
         HIP_CHECK_LAUNCH();
     }
     return JPT_OK;

@@ -22,14 +22,18 @@ u8, u16, u32, u64, f64, vp = (ctypes.c_uint8, ctypes.c_uint16, ctypes.c_uint32, 
 
 JPT_OK, JPT_E_ARG, JPT_E_UNSUPPORTED, JPT_E_CORRUPT, JPT_E_RANGE, JPT_E_BUFSIZE, JPT_E_HIP, JPT_E_CAPACITY = \
     0, -1, -2, -3, -4, -5, -6, -7
-FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR = 0, 1, 2
-CACHE_NONE, CACHE_LRU = 0, 1
+FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR, FILTER_BILINEAR_CLAMPED = 0, 1, 2, 3
+SAMPLING_420, SAMPLING_444 = 420, 444
+FILTER_MIP_OFF = 0x100
+CACHE_NONE, CACHE_LRU, CACHE_EVICT_INVISIBLE, CACHE_HASH = 0, 1, 2, 3
+INDEX_SPLICED, INDEX_PREDICTORS = 0, 1
+SCENE_PREDICTOR_INDEX = 1
 IDCT_MFMA_F16, IDCT_SCALAR_F32, IDCT_FUSED_F32 = 0, 1, 2
 FRAME_AUTO = 0xFFFFFFFF
 TUNE_XCD_TILES = 1
-CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT = range(7)
+CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT, CTR_GRAD_MAX = range(8)
 N_COUNTERS = 16
-ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL, ERR_INTERNAL = 1, 2, 4, 8
+ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL, ERR_INTERNAL, ERR_GRAD = 1, 2, 4, 8, 16
 SLOT_NONE = 0xFFFFFFFF
 TEXEL_INVALID = 0xFFFF00FF
 ITEMS_DU = 6
@@ -43,13 +47,14 @@ class LevelInfo(ctypes.Structure):
                 ("n_mcu", u32), ("blk_cols", u32), ("blk_rows", u32), ("n_records", u32), ("stream_words", u32),
                 ("stream_bits", u64), ("scan_bits", u64), ("removed_dc_bits", u64),
                 ("quant", (u16 * 64) * 2), ("huff_bits", (u8 * 16) * 4), ("huff_vals", (u8 * 256) * 4),
-                ("huff_nvals", u16 * 4), ("reserved0", u16 * 2),
+                ("huff_nvals", u16 * 4), ("index_kind", u16), ("reserved0", u16),
                 ("index_bits_per_mcu", f64), ("dc_bits_per_mcu", f64), ("overhead_bpp_bound", f64),
                 ("overhead_bpp_effective", f64), ("stored_bpp", f64)]
 
 
 class LevelDesc(ctypes.Structure):
-    _fields_ = [("stream", u64), ("records", u64), ("stream_bits", u64), ("width", u32), ("height", u32),
+    _fields_ = [("stream", u64), ("records", u64), ("stream_bits", u32), ("index_kind", u32), ("width", u32),
+                ("height", u32),
                 ("blk_cols", u32), ("blk_rows", u32), ("mcu_cols", u32), ("n_mcu", u32), ("blk_base", u32),
                 ("sampling", u32), ("table_set", u32), ("quant", u32)]
 
@@ -61,7 +66,7 @@ class TextureDesc(ctypes.Structure):
 class SceneC(ctypes.Structure):
     _fields_ = [("levels", vp), ("textures", vp), ("word_level", vp), ("tables", vp), ("quant", vp),
                 ("n_levels", u32), ("n_textures", u32), ("n_tablesets", u32), ("n_quant", u32),
-                ("n_blocks", u32), ("reserved", u32)]
+                ("n_blocks", u32), ("flags", u32)]
 
 
 class ViewC(ctypes.Structure):
@@ -76,7 +81,8 @@ class FrameC(ctypes.Structure):
 
 class CacheC(ctypes.Structure):
     _fields_ = [("texels", vp), ("slot_of", vp), ("owner", vp), ("last_used", vp), ("resident", vp),
-                ("free_stack", vp), ("meta", vp), ("tie_mask", vp), ("n_slots", u32), ("policy", u32)]
+                ("free_stack", vp), ("meta", vp), ("tie_mask", vp), ("n_slots", u32), ("policy", u32),
+                ("hash", vp), ("n_buckets", u32), ("reserved", u32)]
 
 
 LRU_MAX_AGE = 1023
@@ -90,10 +96,13 @@ class TuningC(ctypes.Structure):
 
 assert ctypes.sizeof(LevelDesc) == 64 and ctypes.sizeof(TextureDesc) == 16
 assert ctypes.sizeof(SceneC) == 64 and ctypes.sizeof(ViewC) == 32 and ctypes.sizeof(FrameC) == 48
+assert ctypes.sizeof(CacheC) == 88 and ctypes.sizeof(LevelInfo) == 1464
 
 # name -> (restype, argtypes) of every function the header declares
 SIGNATURES = {
     "jpt_build_index": (ctypes.c_int32, [vp, ctypes.c_size_t, vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t]),
+    "jpt_build_index_ex": (ctypes.c_int32, [vp, ctypes.c_size_t, u32, vp, vp, ctypes.c_size_t, vp,
+                                            ctypes.c_size_t]),
     "jpt_build_tables": (ctypes.c_int32, [vp, vp, ctypes.c_size_t, vp]),
     "jpt_layout": (ctypes.c_int32, [vp, u32, vp, vp, ctypes.c_size_t, vp]),
     "jpt_make_level_desc": (ctypes.c_int32, [vp, u64, u64, u32, u32, u32, vp]),
@@ -101,6 +110,7 @@ SIGNATURES = {
     "jpt_mark_blocks": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
     "jpt_decode_blocks": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_entropy_decode": (ctypes.c_int32, [vp, vp, vp, vp]),
+    "jpt_decode_reduced": (ctypes.c_int32, [vp, vp, u32, vp, vp, vp]),
     "jpt_idct_color": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_resolve": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
     "jpt_cache_reset": (ctypes.c_int32, [vp, vp, vp]),
@@ -110,6 +120,8 @@ SIGNATURES = {
     "jpt_dequantize": (ctypes.c_int32, [vp, vp, vp, u32, vp]),
     "jpt_fwd_float": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, u32, vp, vp, vp]),
     "jpt_backward": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp, vp, u32, vp]),
+    "jpt_geometry_pass": (ctypes.c_int32, [vp, vp, u32, vp, u32, u32, u32, vp, vp]),
+    "jpt_bc1_resolve": (ctypes.c_int32, [vp, vp, u32, u32, vp]),
     "jpt_version": (u32, []),
     "jpt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
 }
@@ -155,15 +167,16 @@ class LevelIndex:
         self.info, self.stream, self.records = info, stream, records
 
 
-def build_index(jpeg: bytes) -> LevelIndex:
+def build_index(jpeg: bytes, kind: int = INDEX_SPLICED) -> LevelIndex:
     buf = np.frombuffer(jpeg, np.uint8)
     info = LevelInfo()
     L = lib()
-    _check("jpt_build_index", L.jpt_build_index(_np_ptr(buf), len(buf), ctypes.byref(info), None, 0, None, 0))
+    _check("jpt_build_index_ex", L.jpt_build_index_ex(_np_ptr(buf), len(buf), kind, ctypes.byref(info), None, 0,
+                                                      None, 0))
     stream = np.zeros(info.stream_words, np.uint32)
     records = np.zeros(info.n_records * RECORD_BYTES, np.uint8)
-    _check("jpt_build_index", L.jpt_build_index(_np_ptr(buf), len(buf), ctypes.byref(info), _np_ptr(stream),
-                                                len(stream), _np_ptr(records), len(records)))
+    _check("jpt_build_index_ex", L.jpt_build_index_ex(_np_ptr(buf), len(buf), kind, ctypes.byref(info),
+                                                      _np_ptr(stream), len(stream), _np_ptr(records), len(records)))
     return LevelIndex(info, stream, records)
 
 
@@ -192,15 +205,16 @@ def _table_key(info: LevelInfo) -> bytes:
 class HostScene:
     """Index build and descriptors of a texture set (no device memory)."""
 
-    def __init__(self, textures, threads: int | None = None):
+    def __init__(self, textures, threads: int | None = None, index_kind: int = INDEX_SPLICED):
         self.textures = textures
+        self.index_kind = index_kind
         jpegs, tex_first, tex_count = [], [], []
         for t in textures:
             tex_first.append(len(jpegs)); tex_count.append(len(t.jpegs))
             jpegs.extend(t.jpegs)
         threads = threads or min(16, os.cpu_count() or 1)
         with ThreadPoolExecutor(threads) as ex:
-            self.levels = list(ex.map(build_index, jpegs))
+            self.levels = list(ex.map(lambda j: build_index(j, index_kind), jpegs))
         self.tex_first = tex_first; self.tex_count = tex_count
         infos = [l.info for l in self.levels]
         self.blk_base, self.word_level, self.n_blocks = layout(infos)
@@ -256,14 +270,16 @@ class HostScene:
         return bytes(arr)
 
     def overhead(self):
-        """(paper-accounting bpp bound, effective bpp, stored bpp) over all levels."""
-        px = sum(l.info.width * l.info.height for l in self.levels)
-        mcu_px = sum(l.info.n_mcu * (256 if l.info.sampling == 420 else 64) for l in self.levels)
-        n_mcu = sum(l.info.n_mcu for l in self.levels)
-        removed = sum(l.info.removed_dc_bits for l in self.levels)
-        per = (32 + 16 * 8) / 9 + 36
-        stored = sum(l.info.n_records * 512 + l.info.stream_bits for l in self.levels)
-        return per * n_mcu / mcu_px, (per * n_mcu - removed) / mcu_px, stored / px
+        """(paper-accounting bpp bound, effective bpp, stored bpp) over all
+        levels: the library's per-level figures (jpt_level_info), weighted by
+        the texels they are per (MCU texels for the first two, image texels
+        for the stored size)."""
+        mcu_px = [l.info.n_mcu * (256 if l.info.sampling == SAMPLING_420 else 64) for l in self.levels]
+        px = [l.info.width * l.info.height for l in self.levels]
+        bound = sum(l.info.overhead_bpp_bound * m for l, m in zip(self.levels, mcu_px)) / sum(mcu_px)
+        eff = sum(l.info.overhead_bpp_effective * m for l, m in zip(self.levels, mcu_px)) / sum(mcu_px)
+        stored = sum(l.info.stored_bpp * p for l, p in zip(self.levels, px)) / sum(px)
+        return bound, eff, stored
 
 
 # ----------------------------------------------------------- device side
@@ -297,7 +313,9 @@ class DeviceScene:
         self.quant_t = _dev_bytes(np.concatenate(host.quants), device)
         self.c = SceneC(self.levels_t.data_ptr(), self.textures_t.data_ptr(), self.word_level_t.data_ptr(),
                         self.tables_t.data_ptr(), self.quant_t.data_ptr(), len(host.levels), len(host.textures),
-                        len(host.tablesets), len(host.quants), host.n_blocks, 0)
+                        len(host.tablesets), len(host.quants), host.n_blocks,
+                        SCENE_PREDICTOR_INDEX if any(l.info.index_kind == INDEX_PREDICTORS for l in host.levels)
+                        else 0)
         self.n_blocks = host.n_blocks
 
     def compressed_bytes(self) -> int:
@@ -337,7 +355,7 @@ class Cache:
         self.slot_of = torch.full((scene.n_blocks,), -1, dtype=torch.int32, device=d)
         self.n_slots = n_slots
         self.policy = policy
-        if policy == CACHE_LRU:
+        if policy in (CACHE_LRU, CACHE_EVICT_INVISIBLE):
             n_words = scene.n_blocks // 32
             self.owner = torch.empty(n_slots, dtype=torch.int32, device=d)
             self.last_used = torch.empty(n_slots, dtype=torch.int32, device=d)
@@ -347,15 +365,31 @@ class Cache:
             self.meta = torch.empty(CACHE_META_WORDS, dtype=torch.int32, device=d)
             self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), self.owner.data_ptr(),
                             self.last_used.data_ptr(), self.resident.data_ptr(), self.free_stack.data_ptr(),
-                            self.meta.data_ptr(), self.tie_mask.data_ptr(), n_slots, policy)
+                            self.meta.data_ptr(), self.tie_mask.data_ptr(), n_slots, policy, None, 0, 0)
+            self.reset(scene, stream)
+        elif policy == CACHE_HASH:
+            nb = 1 << max(4, (2 * n_slots - 1).bit_length())
+            self.owner = torch.empty(n_slots, dtype=torch.int32, device=d)
+            self.free_stack = torch.empty(n_slots, dtype=torch.int32, device=d)
+            self.meta = torch.empty(CACHE_META_WORDS, dtype=torch.int32, device=d)
+            self.hash = torch.empty(2 * nb, dtype=torch.int32, device=d)
+            self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), self.owner.data_ptr(), None, None,
+                            self.free_stack.data_ptr(), self.meta.data_ptr(), None, n_slots, policy,
+                            self.hash.data_ptr(), nb, 0)
             self.reset(scene, stream)
         else:
             self.c = CacheC(self.texels.data_ptr(), self.slot_of.data_ptr(), None, None, None, None, None, None,
-                            n_slots, policy)
+                            n_slots, policy, None, 0, 0)
 
     def reset(self, scene: DeviceScene, stream=None):
         _check("jpt_cache_reset", lib().jpt_cache_reset(ctypes.byref(scene.c), ctypes.byref(self.c),
                                                         stream if stream is not None else current_stream()))
+
+    def hash_entries(self) -> dict:
+        """JPT_CACHE_HASH: {key: slot} of the map's entries (host copy)."""
+        h = self.hash.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        live = h[:, 0] != 0xFFFFFFFF
+        return {int(k): int(v) & 0x7FFFFFFF for k, v in h[live]}
 
     def resident_blocks(self) -> np.ndarray:
         m = self.resident.cpu().numpy().view(np.uint32)
@@ -418,6 +452,14 @@ def decode_blocks(scene: DeviceScene, frame: Frame, cache: Cache, idct_mode: int
         ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
 
 
+def decode_reduced(scene: DeviceScene, frame: Frame, scale_log2: int, out, tuning=None, stream=None):
+    """jpt_decode_reduced into `out` (a device tensor of at least
+    items x (16 >> scale_log2)^2 int32)."""
+    _check("jpt_decode_reduced", lib().jpt_decode_reduced(
+        ctypes.byref(scene.c), ctypes.byref(frame.c), scale_log2, vp(out.data_ptr()),
+        ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
+
+
 def idct_color(scene: DeviceScene, frame: Frame, cache: Cache, idct_mode: int = IDCT_MFMA_F16, tuning=None,
                stream=None):
     _check("jpt_idct_color", lib().jpt_idct_color(
@@ -431,6 +473,65 @@ def resolve(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Ca
         ctypes.byref(tuning) if tuning else None, stream if stream is not None else current_stream()))
 
 
+def geometry_pass(scene: DeviceScene, tris, cam, views: "Views", i: int = 0, stream=None):
+    """jpt_geometry_pass into view i's G-buffer.  tris: a device tensor
+    holding the triangles (synth.TRIANGLE_DTYPE records); cam: one camera
+    record (synth.CAMERA_DTYPE)."""
+    H, W = views.frames[i].shape
+    cam = np.ascontiguousarray(cam)
+    n = tris.numel() // 80
+    _check("jpt_geometry_pass", lib().jpt_geometry_pass(
+        ctypes.byref(scene.c), vp(tris.data_ptr()) if n else None, n, cam.ctypes.data_as(vp), W, H, W,
+        vp(views.gbufs[i].data_ptr()), stream if stream is not None else current_stream()))
+
+
+class Bc1Level(ctypes.Structure):
+    _fields_ = [("blocks", vp), ("width", u32), ("height", u32), ("blocks_per_row", u32), ("reserved", u32)]
+
+
+class Bc1SceneC(ctypes.Structure):
+    _fields_ = [("levels", vp), ("textures", vp), ("n_levels", u32), ("n_textures", u32)]
+
+
+assert ctypes.sizeof(Bc1Level) == 24 and ctypes.sizeof(Bc1SceneC) == 24
+
+
+class Bc1Scene:
+    """BC1 textures resident in HBM (the fixed-rate baseline).  textures:
+    per texture a list of levels (level 0 first), each (blocks, width,
+    height) with `blocks` the level's BC1 bytes."""
+
+    def __init__(self, textures, device="cuda"):
+        blobs, dims, tex = [], [], []
+        for levels in textures:
+            tex.append((len(dims), len(levels), levels[0][1], levels[0][2]))
+            for blk, w, h in levels:
+                assert len(blk) >= ((w + 3) // 4) * ((h + 3) // 4) * 8
+                blobs.append(blk)
+                dims.append((w, h))
+        offs, o = [], 0
+        for b in blobs:
+            offs.append(o)
+            o += (len(b) + 255) // 256 * 256
+        pool = np.zeros(max(o, 256), np.uint8)
+        for b, off in zip(blobs, offs):
+            pool[off:off + len(b)] = np.frombuffer(b, np.uint8)
+        self.pool = _dev_bytes(pool, device)
+        lv = (Bc1Level * len(dims))()
+        for i, ((w, h), off) in enumerate(zip(dims, offs)):
+            lv[i] = Bc1Level(self.pool.data_ptr() + off, w, h, (w + 3) // 4, 0)
+        self.levels_t = _dev_bytes(bytes(lv), device)
+        td = (TextureDesc * len(tex))(*[TextureDesc(*t) for t in tex])
+        self.textures_t = _dev_bytes(bytes(td), device)
+        self.c = Bc1SceneC(self.levels_t.data_ptr(), self.textures_t.data_ptr(), len(dims), len(tex))
+        self.bytes = sum(len(b) for b in blobs)
+
+
+def bc1_resolve(scene: Bc1Scene, views: "Views", filt: int, stream=None):
+    _check("jpt_bc1_resolve", lib().jpt_bc1_resolve(ctypes.byref(scene.c), views.c, views.n, filt,
+                                                    stream if stream is not None else current_stream()))
+
+
 class Renderer:
     """One frame of the plain form: mark -> decode -> resolve on the current
     stream, over one or more views.  `tuning` (TuningC or None) holds launch
@@ -442,7 +543,8 @@ class Renderer:
         self.scene = DeviceScene(self.host, device)
         self.views = Views(gbufs, device)
         self.filter = filt
-        taps = 8 if filt == FILTER_TRILINEAR else (4 if filt == FILTER_BILINEAR else 1)
+        mode = filt & 0xFF
+        taps = 8 if mode == FILTER_TRILINEAR else (1 if mode == FILTER_NEAREST else 4)
         cap = self.host.n_items_total
         self.max_items = int(max_items or min(cap, taps * 4 * self.views.n_pixels + 64))
         self.frame = Frame(self.scene, self.max_items)
@@ -481,7 +583,7 @@ class Renderer:
         or `views`) into a HIP graph (jpt_graph_capture) on `stream`, a
         torch.cuda.Stream other than the default one.  With an LRU cache the
         renderer switches to FRAME_AUTO."""
-        if self.cache.policy == CACHE_LRU:
+        if self.cache.policy in (CACHE_LRU, CACHE_EVICT_INVISIBLE):
             self.frame_no = FRAME_AUTO
         self.frame.c.frame_no = self.frame_no
         return Graph(self, stream, views or self.views)

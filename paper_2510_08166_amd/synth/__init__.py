@@ -54,6 +54,7 @@ def lib():
             L.synth_quant_tables.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
             L.synth_raster.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+            L.synth_bc1_encode.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
             _lib = L
     return _lib
 
@@ -210,17 +211,18 @@ def similarity(tx: float, ty: float, rot_deg: float, zoom: float, W: int, H: int
 class EncodedTexture:
     """One texture: its levels as JPEG files (and the RGB levels when kept)."""
 
-    def __init__(self, tex_id, width, height, quality, sampling, jpegs, rgb_levels=None):
+    def __init__(self, tex_id, width, height, quality, sampling, jpegs, rgb_levels=None, seed=None):
         self.tex_id = tex_id; self.width = width; self.height = height
         self.quality = quality; self.sampling = sampling
         self.jpegs = jpegs; self.rgb_levels = rgb_levels
+        self.seed = seed   # of the procedural base image (synth texture), when generated here
 
 
 def make_texture(seed: int, w: int, h: int, quality: int, sampling: int, n_levels, keep_rgb=False, tex_id=0):
     base = texture(seed, w, h)
     levels = mip_chain(base, n_levels)
     jpegs = [encode(l, quality, sampling) for l in levels]
-    return EncodedTexture(tex_id, w, h, quality, sampling, jpegs, levels if keep_rgb else None)
+    return EncodedTexture(tex_id, w, h, quality, sampling, jpegs, levels if keep_rgb else None, seed=seed)
 
 
 def make_textures(specs, keep_rgb=False, threads: int | None = None, log=None):
@@ -246,3 +248,102 @@ def seed_ints(seed: int, n: int) -> list[int]:
 def target_frame(seed: int, H: int, W: int) -> np.ndarray:
     """Seeded target image for an L2 loss: [H, W, 3] float32, uniform in [0, 255]."""
     return np.random.default_rng(seed).uniform(0.0, 255.0, (H, W, 3)).astype(np.float32)
+
+
+# ------------------------------------------------------------- 3-D scenes
+# Triangles and cameras for the geometry pass (the pass before Mark): the
+# layouts of jpt_triangle (80 bytes) and jpt_camera (64 bytes).
+TRIANGLE_DTYPE = np.dtype([("p0", "<f4", 3), ("p1", "<f4", 3), ("p2", "<f4", 3), ("uv0", "<f4", 2),
+                           ("uv1", "<f4", 2), ("uv2", "<f4", 2), ("tex", "<u4"), ("reserved", "<u4", 4)])
+CAMERA_DTYPE = np.dtype([("eye", "<f4", 3), ("fwd", "<f4", 3), ("right", "<f4", 3), ("up", "<f4", 3),
+                         ("tan_half_x", "<f4"), ("tan_half_y", "<f4"), ("reserved", "<f4", 2)])
+assert TRIANGLE_DTYPE.itemsize == 80 and CAMERA_DTYPE.itemsize == 64
+
+
+def quad_triangles(corner, e1, e2, uv_scale, tex):
+    """Two triangles covering corner + a e1 + b e2 (a, b in [0, 1]) with
+    uv = (a su, b sv)."""
+    c = np.asarray(corner, np.float64); e1 = np.asarray(e1, np.float64); e2 = np.asarray(e2, np.float64)
+    su, sv = uv_scale
+    t = np.zeros(2, TRIANGLE_DTYPE)
+    t[0]["p0"], t[0]["p1"], t[0]["p2"] = c, c + e1, c + e1 + e2
+    t[0]["uv0"], t[0]["uv1"], t[0]["uv2"] = (0, 0), (su, 0), (su, sv)
+    t[1]["p0"], t[1]["p1"], t[1]["p2"] = c, c + e1 + e2, c + e2
+    t[1]["uv0"], t[1]["uv1"], t[1]["uv2"] = (0, 0), (su, sv), (0, sv)
+    t["tex"] = tex
+    return t
+
+
+def room_scene(seed: int, n_tex: int, size=24.0, height=8.0, panels=6, n_boxes=24, texels_per_unit=256.0,
+               tex_side=2048):
+    """An atrium-like room (a stand-in for the paper's Sponza): floor,
+    ceiling and four walls cut into panels, and boxes (pillars and crates)
+    inside, every face a textured quad with a seeded texture id; uv
+    scales give about `texels_per_unit` texels per world unit.  Returns the
+    triangles (TRIANGLE_DTYPE)."""
+    rng = np.random.default_rng(seed)
+    tris = []
+    s = size / 2.0
+    rep = texels_per_unit / tex_side
+
+    def add(corner, e1, e2):
+        l1, l2 = np.linalg.norm(e1), np.linalg.norm(e2)
+        tris.append(quad_triangles(corner, e1, e2, (l1 * rep, l2 * rep), int(rng.integers(0, n_tex))))
+
+    step = size / panels
+    for i in range(panels):
+        for j in range(panels):
+            add((-s + i * step, 0.0, -s + j * step), (step, 0, 0), (0, 0, step))        # floor
+            add((-s + i * step, height, -s + j * step), (0, 0, step), (step, 0, 0))     # ceiling
+    hs = height / 2
+    for i in range(panels):
+        for j in range(2):
+            a = -s + i * step
+            add((a, j * hs, -s), (step, 0, 0), (0, hs, 0))                # wall z = -s
+            add((a + step, j * hs, s), (-step, 0, 0), (0, hs, 0))         # wall z = +s
+            add((-s, j * hs, a + step), (0, 0, -step), (0, hs, 0))        # wall x = -s
+            add((s, j * hs, a), (0, 0, step), (0, hs, 0))                 # wall x = +s
+    for _ in range(n_boxes):
+        cx, cz = rng.uniform(-s * 0.8, s * 0.8, 2)
+        if abs(cx) < 2.0 and abs(cz) < 2.0:
+            cx += 3.0 * np.sign(cx or 1.0)
+        w, d = rng.uniform(0.4, 1.6, 2)
+        h = rng.uniform(0.5, height) if rng.random() < 0.5 else height
+        x0, x1, z0, z1 = cx - w / 2, cx + w / 2, cz - d / 2, cz + d / 2
+        add((x0, 0, z0), (w, 0, 0), (0, h, 0))
+        add((x1, 0, z1), (-w, 0, 0), (0, h, 0))
+        add((x0, 0, z1), (0, 0, -d), (0, h, 0))
+        add((x1, 0, z0), (0, 0, d), (0, h, 0))
+        add((x0, h, z0), (0, 0, d), (w, 0, 0))
+    return np.concatenate(tris)
+
+
+def camera(eye, yaw_deg: float, pitch_deg: float, fov_x_deg: float, W: int, H: int) -> np.ndarray:
+    """A pinhole camera at `eye` turned by yaw (about the vertical axis, from
+    looking along -z) and pitch; square pixels."""
+    yaw, pitch = np.radians(yaw_deg), np.radians(pitch_deg)
+    fwd = np.array([np.sin(yaw) * np.cos(pitch), np.sin(pitch), -np.cos(yaw) * np.cos(pitch)])
+    right = np.array([np.cos(yaw), 0.0, np.sin(yaw)])
+    up = np.cross(right, fwd)
+    c = np.zeros(1, CAMERA_DTYPE)
+    c["eye"], c["fwd"], c["right"], c["up"] = eye, fwd, right, up
+    tx = np.tan(np.radians(fov_x_deg) / 2)
+    c["tan_half_x"], c["tan_half_y"] = tx, tx * H / W
+    return c
+
+
+# ---------------------------------------------------------------- BC1 input
+def bc1_encode(rgb: np.ndarray) -> bytes:
+    """A simple BC1 encoder for the fixed-rate baseline (the paper's
+    Background: BC1), in C (synth_bc1_encode): per 4x4 block (edges
+    replicated) the endpoints are the block's darkest and brightest texels
+    by luma, rounded to RGB565, ordered so that colour 0 > colour 1
+    (four-colour mode; equal endpoints give an all-zero index block), and
+    every texel takes the palette entry nearest in RGB.  8 bytes per block,
+    row-major blocks."""
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    h, w = rgb.shape[:2]
+    out = np.zeros(((h + 3) // 4) * ((w + 3) // 4) * 8, np.uint8)
+    if lib().synth_bc1_encode(_ptr(rgb), w, h, _ptr(out)) != 0:
+        raise RuntimeError("synth_bc1_encode failed")
+    return out.tobytes()

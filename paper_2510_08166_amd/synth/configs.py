@@ -17,7 +17,8 @@ import numpy as np
 
 from . import GPIXEL_DTYPE, make_textures, random_quads, rasterise, seed_ints
 
-FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR = 0, 1, 2
+FILTER_NEAREST, FILTER_BILINEAR, FILTER_TRILINEAR, FILTER_BILINEAR_CLAMPED = 0, 1, 2, 3
+FILTER_MIP_OFF = 0x100
 
 
 class Workload:

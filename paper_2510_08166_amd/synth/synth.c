@@ -453,3 +453,66 @@ int synth_raster(int W, int H, int nq, const double *Ginv, const int *bbox,
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ BC1 */
+/* A simple BC1 encoder (input for the fixed-rate baseline): per 4x4 block,
+ * edges replicated, the endpoints are the darkest and brightest texels by
+ * luma (299 R + 587 G + 114 B), rounded to RGB565 and ordered so that
+ * colour 0 > colour 1 (four-colour mode; equal endpoints give index 0
+ * everywhere); each texel takes the nearest palette entry in RGB (the
+ * first on ties).  out: 8 bytes per block, row-major. */
+static uint32_t to565(const int *c) {
+    return (uint32_t)(((c[0] * 31 + 127) / 255) << 11 | ((c[1] * 63 + 127) / 255) << 5 | ((c[2] * 31 + 127) / 255));
+}
+static void from565(uint32_t v, int *c) {
+    int r = (v >> 11) & 31, g = (v >> 5) & 63, b = v & 31;
+    c[0] = (r << 3) | (r >> 2); c[1] = (g << 2) | (g >> 4); c[2] = (b << 3) | (b >> 2);
+}
+
+int synth_bc1_encode(const uint8_t *rgb, int w, int h, uint8_t *out) {
+    if (!rgb || !out || w <= 0 || h <= 0) return -1;
+    const int bw = (w + 3) / 4, bh = (h + 3) / 4;
+    for (int by = 0; by < bh; by++)
+        for (int bx = 0; bx < bw; bx++) {
+            int t[16][3];
+            for (int j = 0; j < 4; j++)
+                for (int i = 0; i < 4; i++) {
+                    int x = 4 * bx + i, y = 4 * by + j;
+                    if (x >= w) x = w - 1;
+                    if (y >= h) y = h - 1;
+                    for (int c = 0; c < 3; c++) t[4 * j + i][c] = rgb[((size_t)y * w + x) * 3 + c];
+                }
+            int lo = 0, hi = 0;
+            long llo = 1L << 40, lhi = -1;
+            for (int k = 0; k < 16; k++) {
+                long l = 299L * t[k][0] + 587L * t[k][1] + 114L * t[k][2];
+                if (l < llo) { llo = l; lo = k; }
+                if (l > lhi) { lhi = l; hi = k; }
+            }
+            uint32_t c0 = to565(t[hi]), c1 = to565(t[lo]);
+            if (c0 < c1) { uint32_t x = c0; c0 = c1; c1 = x; }
+            int p[4][3];
+            from565(c0, p[0]);
+            from565(c1, p[1]);
+            for (int c = 0; c < 3; c++) {
+                p[2][c] = (2 * p[0][c] + p[1][c] + 1) / 3;
+                p[3][c] = (p[0][c] + 2 * p[1][c] + 1) / 3;
+            }
+            uint32_t bits = 0;
+            if (c0 != c1)
+                for (int k = 0; k < 16; k++) {
+                    int best = 0;
+                    long bd = -1;
+                    for (int e = 0; e < 4; e++) {
+                        long d = 0;
+                        for (int c = 0; c < 3; c++) d += (long)(t[k][c] - p[e][c]) * (t[k][c] - p[e][c]);
+                        if (bd < 0 || d < bd) { bd = d; best = e; }
+                    }
+                    bits |= (uint32_t)best << (2 * k);
+                }
+            uint8_t *o = out + ((size_t)by * bw + bx) * 8;
+            o[0] = c0 & 255; o[1] = c0 >> 8; o[2] = c1 & 255; o[3] = c1 >> 8;
+            o[4] = bits & 255; o[5] = (bits >> 8) & 255; o[6] = (bits >> 16) & 255; o[7] = bits >> 24;
+        }
+    return 0;
+}

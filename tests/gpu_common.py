@@ -24,10 +24,10 @@ def run(wl, idct_mode=0, **kw):
     return r, ctr, items, coef, tiles, frames
 
 
-def full_parity(wl, coef_sample=None, texel_sample=None, full_render=True, idct_mode=0, tuning=None):
+def full_parity(wl, coef_sample=None, texel_sample=None, full_render=True, idct_mode=0, tuning=None, host=None):
     from paper_2510_08166_amd import jpt
     osc = oracle.Scene(wl.textures)
-    r, ctr, items, coef, tiles, frames = run(wl, idct_mode, tuning=tuning)
+    r, ctr, items, coef, tiles, frames = run(wl, idct_mode, tuning=tuning, host=host)
     print("%s: items %d new %d visible %d err %x" % (wl.name, ctr[jpt.CTR_ITEMS], ctr[jpt.CTR_NEW],
                                                      ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_ERROR]), flush=True)
     assert ctr[jpt.CTR_ERROR] == 0

@@ -53,14 +53,14 @@ def check_grad(g, g64, what):
     assert err <= GRAD_MAX_REL * scale and l2 <= GRAD_L2_REL
 
 
-def vjp_parity(wl, seed=0):
+def vjp_parity(wl, seed=0, scale=1.0):
     r, diff, F = gpu_case(wl)
     items = r.frame.work_items()
     osc, F64 = oracle_case(wl, items)
     assert np.array_equal(F.cpu().numpy().astype(np.float64), F64)
     frame = diff.forward(F)
     rng = np.random.default_rng(seed)
-    dframe = [rng.standard_normal(g.shape + (3,)) for g in wl.views]
+    dframe = [rng.standard_normal(g.shape + (3,)) * scale for g in wl.views]
     dflat = torch.from_numpy(np.concatenate([d.reshape(-1, 3) for d in dframe]).astype(np.float32)).cuda()
     dF = diff.backward(dflat, tuple(F.shape))
     dF2 = diff.backward(dflat, tuple(F.shape))
@@ -83,6 +83,17 @@ def vjp_parity(wl, seed=0):
 @pytest.mark.parametrize("filt", [oracle.NEAREST, oracle.BILINEAR, oracle.TRILINEAR])
 def test_reduced_vjp(gpu, filt):
     vjp_parity(configs.reduced(seed=7, filt=filt))
+
+
+@pytest.mark.parametrize("scale", ["mean", 1e-6, 1e6])
+def test_vjp_at_any_loss_scale(gpu, scale):
+    """dL/dframe of a mean-reduced loss (entries of order 1/(3 x pixels)),
+    and of losses scaled by 1e-6 and 1e6: the backward's fixed-point unit
+    follows max |dL/dframe|, so the gradient keeps the same relative
+    accuracy (and does not overflow)."""
+    wl = configs.reduced(seed=8, filt=oracle.BILINEAR)
+    s = 1.0 / (3 * wl.n_pixels) if scale == "mean" else scale
+    vjp_parity(wl, seed=3, scale=s)
 
 
 def test_mixed_sampling_ragged_trilinear(gpu):

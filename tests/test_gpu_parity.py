@@ -328,3 +328,102 @@ def test_wide_coefficients(gpu, sampling, q, dc_max, density, mode):
     wl = configs.Workload("wide q%d %d" % (q, sampling), tex, [g], configs.FILTER_NEAREST)
     r, osc, blocks = full_parity(wl, idct_mode=mode)
     assert len(blocks) == ((w + 15) // 16) * ((h + 15) // 16)
+
+
+@pytest.mark.parametrize("filt", [configs.FILTER_BILINEAR_CLAMPED,
+                                  configs.FILTER_BILINEAR_CLAMPED | configs.FILTER_MIP_OFF,
+                                  configs.FILTER_NEAREST | configs.FILTER_MIP_OFF,
+                                  configs.FILTER_TRILINEAR | configs.FILTER_MIP_OFF])
+def test_paper_variants_clamped_and_mip_off(gpu, filt):
+    """The paper's single-MCU clamped bilinear (centre-only marking) and its
+    rows without mip mapping, against the oracle's definitions."""
+    wl = configs.reduced(seed=12, filt=filt)
+    r, osc, blocks = full_parity(wl)
+    if filt & 0xFF == configs.FILTER_BILINEAR_CLAMPED:
+        near, _ = osc.mark(wl.views[0], configs.FILTER_NEAREST | (filt & configs.FILTER_MIP_OFF))
+        assert np.array_equal(blocks, near)
+
+
+def test_evict_invisible_policy(gpu):
+    """The paper's Update Cache: after each frame every block the frame did
+    not read leaves the cache; decoded and evicted sets equal the oracle's
+    simulator, frames match the oracle."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    wl, _ = lru_gap_workload()
+    osc = oracle.Scene(wl.textures)
+    vis_sets = [parity.visible_blocks(osc, [g], wl.filter) for g in wl.views]
+    cap = max(len(v) for v in vis_sets) + 8
+    r = jpt.Renderer(wl.textures, [wl.views[0]], wl.filter, n_slots=cap, policy=jpt.CACHE_EVICT_INVISIBLE)
+    sim = oracle.EvictInvisibleSim(cap)
+    lc = parity.LevelCache(osc)
+    for f, (g, V) in enumerate(zip(wl.views, vis_sets)):
+        r.set_views([g])
+        r.render()
+        torch.cuda.synchronize()
+        ctr = r.frame.counters_host()
+        new, ev = sim.step(V)
+        print("frame %d: visible %d new %d evicted %d (oracle %d) err %x" % (
+            f, ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_NEW], ctr[jpt.CTR_EVICTED], len(ev), ctr[jpt.CTR_ERROR]), flush=True)
+        assert ctr[jpt.CTR_ERROR] == 0
+        assert np.array_equal(r.frame.work_items(), parity.expected_items(osc, np.array(new, np.uint32)))
+        assert ctr[jpt.CTR_EVICTED] == len(ev)
+        assert np.array_equal(r.cache.resident_blocks(), np.array(sorted(sim.resident), np.uint32))
+        slot_of = r.cache.slot_of.cpu().numpy().view(np.uint32)
+        tiles = r.cache.texels.cpu().numpy().view(np.uint32).reshape(-1, 256)[slot_of[V]]
+        maxd, nmis, tie, dist, n = parity.check_texels(lc, V, tiles)
+        assert maxd <= 1 and tie <= 1.0
+        ref, bad = osc.resolve(g, wl.filter, parity.levels_from_tiles(osc, V, tiles))
+        assert np.array_equal(r.views.frame_host(), ref)
+
+
+def test_hash_map_cache(gpu):
+    """The paper's hash-map block cache (16/13/3-bit keys, atomicCAS in mark,
+    a probe per tap in resolve, invisible blocks evicted): per frame the
+    decoded set (in insertion order, so compared as a set) and the evicted
+    count equal the evict-invisible simulator, every visible block's key maps
+    to a slot holding its texels, and frames equal the oracle's resolve of
+    those texels."""
+    import torch
+    from paper_2510_08166_amd import jpt, synth
+    wl0 = configs.quad_scene(71, 5, 256, 50, 90, 5, 320, 200, 30, filt=configs.FILTER_BILINEAR)
+    sizes = {i: (256.0, 256.0) for i in range(5)}
+    rng = np.random.default_rng(72)
+    scenes = [wl0.views[0]] + [synth.rasterise(320, 200, synth.random_quads(rng, 320, 200, 30, list(range(5)), sizes))
+                               for _ in range(3)]
+    order = [0, 1, 1, 2, 0, 3, 3, 1]
+    osc = oracle.Scene(wl0.textures)
+    vis_sets = [parity.visible_blocks(osc, [scenes[i]], wl0.filter) for i in order]
+    cap = max(len(v) for v in vis_sets) + 16
+    r = jpt.Renderer(wl0.textures, [scenes[0]], wl0.filter, n_slots=cap, policy=jpt.CACHE_HASH)
+    sim = oracle.EvictInvisibleSim(cap)
+    lc = parity.LevelCache(osc)
+    for f, (i, V) in enumerate(zip(order, vis_sets)):
+        g = scenes[i]
+        r.set_views([g])
+        r.render()
+        torch.cuda.synchronize()
+        ctr = r.frame.counters_host()
+        new, ev = sim.step(V)
+        items = r.frame.work_items()
+        print("frame %d: visible %d new %d evicted %d (oracle %d) err %x" % (
+            f, ctr[jpt.CTR_VISIBLE], ctr[jpt.CTR_NEW], ctr[jpt.CTR_EVICTED], len(ev), ctr[jpt.CTR_ERROR]), flush=True)
+        assert ctr[jpt.CTR_ERROR] == 0
+        assert ctr[jpt.CTR_VISIBLE] == len(V)
+        assert np.array_equal(np.sort(items), parity.expected_items(osc, np.array(new, np.uint32)))
+        assert ctr[jpt.CTR_EVICTED] == len(ev)
+        # the map: every visible block's key -> its slot
+        ent = r.cache.hash_entries()
+        slots = []
+        for b in V:
+            L, bx, by = osc.block_coords(int(b))
+            t = int(np.searchsorted(osc.tex_first, L, side="right") - 1)
+            key = ((by * int(osc.blk_cols[L]) + bx) << 16) | (t << 3) | (L - int(osc.tex_first[t]))
+            assert key in ent
+            slots.append(ent[key])
+        tex = r.cache.texels.cpu().numpy().view(np.uint32).reshape(-1, 256)
+        tiles = tex[np.array(slots)]
+        maxd, nmis, tie, dist, n = parity.check_texels(lc, V, tiles)
+        assert maxd <= 1 and tie <= 1.0
+        ref, bad = osc.resolve(g, wl0.filter, parity.levels_from_tiles(osc, V, tiles))
+        assert np.array_equal(r.views.frame_host(), ref)

@@ -155,7 +155,7 @@ def test_errors():
 def test_library_exports_every_declared_function():
     hdr = open(jpt.os.path.join(jpt.os.path.dirname(jpt._PKG), "include", "jpt.h")).read()
     hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
-    names = set(re.findall(r"\b(jpt_[a-z_]+)\s*\(", hdr))
+    names = set(re.findall(r"\b(jpt_[a-z0-9_]+)\s*\(", hdr))
     assert names, "no declarations found"
     L = ctypes.CDLL(jpt.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(L, n)]
@@ -171,3 +171,52 @@ def test_device_calls_reject_bad_arguments_without_gpu():
     assert L.jpt_mark_blocks(ctypes.byref(sc), None, 0, 7, ctypes.byref(fr), None, None, None) == jpt.JPT_E_ARG
     assert L.jpt_decode_blocks(ctypes.byref(sc), ctypes.byref(fr), None, 0, None, None) == jpt.JPT_E_ARG
     assert L.jpt_resolve(ctypes.byref(sc), None, 0, 0, None, None, None, None) == jpt.JPT_E_ARG
+
+
+# ------------------------------------------- the predictor index reading
+def predicted_equals_sequential(data):
+    li = jpt.build_index(data, jpt.INDEX_PREDICTORS)
+    j = oracle.Jpeg(data)
+    coef, mb, pred, dcb = j.decode()
+    inf = li.info
+    assert inf.index_kind == jpt.INDEX_PREDICTORS
+    assert inf.removed_dc_bits == 0 and inf.stream_bits == inf.scan_bits == mb[-1]
+    assert abs(inf.overhead_bpp_effective - inf.overhead_bpp_bound) < 1e-12
+    rec = li.records.reshape(-1, 64)
+    for m in range(j.n_mcu):
+        # the record's offset is the MCU's start in the original segment and
+        # its fields are the predictors the sequential decode had there
+        g, r = divmod(m, 9)
+        bits = np.unpackbits(rec[g], bitorder="little")
+        anchor = int(np.packbits(bits[0:32], bitorder="little").view(np.uint32)[0])
+        rel = 0 if r == 0 else int(np.packbits(bits[32 + 16 * (r - 1):48 + 16 * (r - 1)],
+                                                bitorder="little").view(np.uint16)[0])
+        assert anchor + rel == mb[m]
+        for c in range(3):
+            f = bits[160 + 12 * (3 * r + c):172 + 12 * (3 * r + c)]
+            v = int(sum(int(x) << i for i, x in enumerate(f)))
+            assert (v - 4096 if v >= 2048 else v) == pred[m, c]
+        rc, out, end = j.decode_predicted_mcu(li.stream, inf.stream_bits, li.records, m)
+        assert rc == 0 and np.array_equal(out, coef[m]) and end == mb[m + 1], m
+    return li
+
+
+@pytest.mark.parametrize("smp", [420, 444])
+@pytest.mark.parametrize("q", [5, 50, 95])
+def test_predictor_index_matches_sequential(smp, q):
+    rgb = synth.texture(q * 11 + smp, 136, 88)
+    data = synth.encode(rgb, q, smp)
+    li = predicted_equals_sequential(data)
+    # the stream is the untouched segment: the spliced one is shorter by the removed DC codes
+    sp = jpt.build_index(data)
+    assert li.info.stream_bits == sp.info.stream_bits + sp.info.removed_dc_bits
+    # the paper's bound, nothing removed: (32 + 8 * 16) / 9 + 36 bits per MCU
+    ms = 16 if smp == 420 else 8
+    assert abs(li.info.overhead_bpp_bound - ((32 + 16 * 8) / 9 + 36) / (ms * ms)) < 1e-12
+
+
+def test_predictor_index_on_pil_files_with_optimised_tables():
+    rgb = synth.texture(78, 120, 72)
+    b = io.BytesIO()
+    Image.fromarray(rgb).save(b, format="JPEG", quality=85, subsampling=2, optimize=True)
+    predicted_equals_sequential(b.getvalue())

@@ -287,3 +287,96 @@ def test_trilinear_weight_at_non_dyadic_lod(small_scene, lod, t):
     b, _ = s.resolve(gb(u, v, lod=float(lo + 1)), BILINEAR, lv)
     A = oracle.unpack_frame(a)[..., :3].astype(int); B = oracle.unpack_frame(b)[..., :3].astype(int)
     assert np.array_equal(oracle.unpack_frame(tr)[..., :3], (A * (256 - t) + B * t + 128) >> 8)
+
+
+@pytest.mark.parametrize("threads", [1, 3])
+def test_cpu_ondemand_baseline_equals_full_render(threads):
+    """The CPU on-demand baseline (decode only the marked blocks through the
+    oracle's per-MCU index, then resolve) gives the plain definition's
+    frame bit for bit, with 4:2:0 and 4:4:4 levels and trilinear taps."""
+    wl = configs.heavy(seed=34, n_tex=6, sides=(64, 128), W=160, H=100, n_quads=16, n_frames=1)
+    s = oracle.Scene(wl.textures)
+    od = oracle.OnDemand(s)
+    ref, vis, _ = s.render(wl.views[0], wl.filter)
+    f, t, n, bad = od.frame(wl.views[0], wl.filter, threads)
+    assert bad == 0 and n == len(vis)
+    assert np.array_equal(f, ref)
+
+
+BILINEAR_CLAMPED, NO_MIP = oracle.BILINEAR_CLAMPED, oracle.NO_MIP
+
+
+def test_clamped_bilinear_marks_the_centre_block_only(small_scene):
+    """Centre-only marking: the clamped filter's footprint is the block of
+    the nearest filter's texel, so it marks exactly what nearest marks."""
+    s = small_scene
+    rng = np.random.default_rng(12)
+    g = gb(rng.normal(0.5, 1.5, (24, 24)), rng.normal(0.5, 1.5, (24, 24)), tex=rng.integers(0, 2, (24, 24)),
+           lod=rng.uniform(-1, 4, (24, 24)))
+    a, _ = s.mark(g, BILINEAR_CLAMPED)
+    b, _ = s.mark(g, NEAREST)
+    assert np.array_equal(a, b)
+
+
+def test_clamped_bilinear_closed_forms(small_scene):
+    """Inside a block the clamped filter is bilinear; across a block border
+    the tap in the other block reads the centre texel's column (or row):
+    s = 15.75 has taps 15 and 16 with weights 64/192 and centre texel 16
+    (block 1), so the pixel is texel 16; s = 15.25 (centre 15, block 0)
+    gives texel 15; s = 16.25 is inside block 1 and stays bilinear."""
+    s = small_scene
+    rng = np.random.default_rng(13)
+    img = _level_image(rng, s, 0)
+    t = img.astype(np.int64)
+    y = np.arange(64)
+    lv = {0: img}
+
+    def px(sx):
+        g = gb(np.full(64, (sx + 0.5) / 64), (y + 0.5) / 64)
+        f, bad = s.resolve(g, BILINEAR_CLAMPED, lv)
+        assert bad == 0
+        return oracle.unpack_frame(f)[0, :, :3].astype(np.int64)
+
+    assert np.array_equal(px(15.75), t[:, 16])
+    assert np.array_equal(px(15.25), t[:, 15])
+    assert np.array_equal(px(16.25), (t[:, 16] * 192 + t[:, 17] * 64 + 128) >> 8)
+    # and across the wrap at the last column: s = 63.75 -> centre 0 (block 0), tap 63 clamps to 0
+    assert np.array_equal(px(63.75), t[:, 0])
+    # interior pixels of random G-buffers equal plain bilinear
+    u = rng.uniform(0, 1, (16, 16)).astype(np.float32); v = rng.uniform(0, 1, (16, 16)).astype(np.float32)
+    sx = u * np.float32(64) - np.float32(0.5); sy = v * np.float32(64) - np.float32(0.5)
+    inside = ((np.floor(sx) % 64) // 16 == ((np.floor(sx) + 1) % 64) // 16) & \
+             ((np.floor(sy) % 64) // 16 == ((np.floor(sy) + 1) % 64) // 16)
+    a, _ = s.resolve(gb(u, v), BILINEAR_CLAMPED, lv)
+    b, _ = s.resolve(gb(u, v), BILINEAR, lv)
+    assert inside.sum() > 100 and np.array_equal(a[inside], b[inside])
+
+
+@pytest.mark.parametrize("filt", [NEAREST, BILINEAR, TRILINEAR, BILINEAR_CLAMPED])
+def test_no_mip_samples_level_zero(small_scene, filt):
+    """Mip mapping off: the same as every pixel at lod 0 (level 0 only)."""
+    s = small_scene
+    rng = np.random.default_rng(14)
+    g = gb(rng.normal(0.5, 1.5, (20, 20)), rng.normal(0.5, 1.5, (20, 20)), tex=rng.integers(0, 2, (20, 20)),
+           lod=rng.uniform(-1, 6, (20, 20)))
+    g0 = g.copy()
+    g0["lod"] = 0.0
+    lv = {L: s.decode_level(L) for L in range(len(s.jpegs))}
+    a, _ = s.resolve(g, filt | NO_MIP, lv)
+    b, _ = s.resolve(g0, filt, lv)
+    assert np.array_equal(a, b)
+    va, _ = s.mark(g, filt | NO_MIP)
+    vb, _ = s.mark(g0, filt)
+    assert np.array_equal(va, vb)
+
+
+def test_evict_invisible_hand_trace():
+    """The paper's policy: whatever a frame does not read leaves the cache."""
+    sim = oracle.EvictInvisibleSim(10)
+    assert sim.step({1, 2, 3}) == ([1, 2, 3], [])
+    assert sim.step({2, 3, 4}) == ([4], [1])
+    assert sim.step({5}) == ([5], [2, 3, 4])
+    assert sim.step({5}) == ([], [])
+    assert sim.step({1, 5}) == ([1], [])        # 1 was evicted two frames ago: decoded again
+    with pytest.raises(oracle.OracleError):
+        sim.step(set(range(11)))
