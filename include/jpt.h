@@ -350,6 +350,31 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results nev
  * interleaving neighbouring tiles over all of them. */
 #define JPT_TUNE_XCD_TILES 1u
 
+/* Buffer sizes for rendering a scene's views under `filter` (host query,
+ * no device access): what jpt_frame and jpt_cache need so that no frame of
+ * these views can overflow them.  A pixel reads at most T blocks (nearest
+ * and the one-MCU clamp 1, bilinear 4, trilinear 8); a block is one work
+ * item (4:2:0) or four (4:4:4); so a frame lists at most
+ * min(items of the scene, T x 4:4:4-factor x pixels) work items and reads
+ * at most min(blocks of the scene, T x pixels) blocks.
+ *   infos   n_levels level infos in scene order (host), as for jpt_layout
+ *   views   n_views views; only width and height are read (host)
+ *   out     host, filled on JPT_OK
+ * Errors: JPT_E_ARG (NULL, filter), JPT_E_CAPACITY (as jpt_layout). */
+typedef struct jpt_sizes {
+    uint32_t n_blocks;            /* block ids (jpt_layout) */
+    uint32_t vis_words;           /* frame->vis, cache->resident, cache->tie_mask: u32 words */
+    uint32_t scan_entries;        /* frame->scan: u64 entries (jpt_scan_entries) */
+    uint32_t max_items;           /* frame->work and frame->max_items */
+    uint64_t coef_entries;        /* frame->coef: max_items * 6 * 64 int16 */
+    uint32_t max_blocks;          /* blocks one frame can read: the slots a JPT_CACHE_NONE cache needs */
+    uint32_t items_total;         /* work items of the whole scene (every MCU) */
+    uint64_t texel_words;         /* cache->texels for max_blocks slots (256 u32 each) */
+    uint64_t pixels;              /* pixels of all views */
+} jpt_sizes;
+jpt_status jpt_query_sizes(const jpt_level_info *infos, uint32_t n_levels, const jpt_view *views, uint32_t n_views,
+                           uint32_t filter, jpt_sizes *out);
+
 /* Entries of jpt_frame.scan for a scene of n_blocks block ids: per-tile
  * and per-group counts of the block bitmask (an LRU frame also takes two
  * per-tile scans of it and sums its tiles into the group counts). */

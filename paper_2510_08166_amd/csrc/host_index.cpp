@@ -1,6 +1,7 @@
 // Host side of libjpt: the offline per-level index (paper, Implementation
 // details: "Indexing Table" and "Memory Overhead"), the GPU decode tables and
 // the scene's block-id layout.  Plain C++17, no HIP calls.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -516,6 +517,40 @@ extern "C" uint32_t jpt_scan_entries(uint32_t n_blocks) {
     const uint32_t words = (n_blocks + 31) / 32;
     const uint32_t tiles = (words + JPT_SCAN_TILE_WORDS - 1) / JPT_SCAN_TILE_WORDS;
     return 3 * tiles + (tiles + 255) / 256 * 16 + 1;  // 16 count slots per group of 256 tiles
+}
+
+extern "C" jpt_status jpt_query_sizes(const jpt_level_info *infos, uint32_t n_levels, const jpt_view *views,
+                                      uint32_t n_views, uint32_t filter, jpt_sizes *out) {
+    if (!infos || !out || (n_views && !views)) return JPT_E_ARG;
+    const uint32_t mode = filter & 0xFFu;
+    if (mode > JPT_FILTER_BILINEAR_CLAMPED || (filter & ~0x1FFu)) return JPT_E_ARG;
+    const uint64_t taps = mode == JPT_FILTER_TRILINEAR ? 8 : (mode == JPT_FILTER_BILINEAR ? 4 : 1);
+    uint64_t blocks = 0, items = 0, next = 0;
+    bool any444 = false;
+    for (uint32_t l = 0; l < n_levels; l++) {
+        const uint64_t b = (uint64_t)infos[l].blk_cols * infos[l].blk_rows;
+        const bool s444 = infos[l].sampling == JPT_SAMPLING_444;
+        any444 |= s444;
+        blocks += b;
+        items += s444 ? 4 * b : b;
+        next = (next + b + 31) & ~uint64_t(31);
+        if (next > (1ull << 29)) return JPT_E_CAPACITY;
+    }
+    uint64_t px = 0;
+    for (uint32_t v = 0; v < n_views; v++) px += (uint64_t)views[v].width * views[v].height;
+    const uint64_t max_blocks = std::min(blocks, taps * px);
+    const uint64_t max_items = std::min(items, taps * (any444 ? 4 : 1) * px);
+    std::memset(out, 0, sizeof *out);
+    out->n_blocks = (uint32_t)next;
+    out->vis_words = (uint32_t)(next / 32);
+    out->scan_entries = jpt_scan_entries((uint32_t)next);
+    out->max_items = (uint32_t)max_items;  // (<= 4 x 2^29)
+    out->coef_entries = max_items * JPT_ITEMS_DU * 64;
+    out->max_blocks = (uint32_t)max_blocks;
+    out->items_total = (uint32_t)items;
+    out->texel_words = max_blocks * 256;
+    out->pixels = px;
+    return JPT_OK;
 }
 
 extern "C" uint32_t jpt_version(void) { return JPT_ABI_VERSION; }

@@ -85,6 +85,12 @@ class CacheC(ctypes.Structure):
                 ("hash", vp), ("n_buckets", u32), ("reserved", u32)]
 
 
+class SizesC(ctypes.Structure):
+    _fields_ = [("n_blocks", u32), ("vis_words", u32), ("scan_entries", u32), ("max_items", u32),
+                ("coef_entries", u64), ("max_blocks", u32), ("items_total", u32), ("texel_words", u64),
+                ("pixels", u64)]
+
+
 LRU_MAX_AGE = 1023
 CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1 + 2048 + 2048 + 1024
 
@@ -96,7 +102,7 @@ class TuningC(ctypes.Structure):
 
 assert ctypes.sizeof(LevelDesc) == 64 and ctypes.sizeof(TextureDesc) == 16
 assert ctypes.sizeof(SceneC) == 64 and ctypes.sizeof(ViewC) == 32 and ctypes.sizeof(FrameC) == 48
-assert ctypes.sizeof(CacheC) == 88 and ctypes.sizeof(LevelInfo) == 1464
+assert ctypes.sizeof(CacheC) == 88 and ctypes.sizeof(LevelInfo) == 1464 and ctypes.sizeof(SizesC) == 48
 
 # name -> (restype, argtypes) of every function the header declares
 SIGNATURES = {
@@ -107,6 +113,7 @@ SIGNATURES = {
     "jpt_layout": (ctypes.c_int32, [vp, u32, vp, vp, ctypes.c_size_t, vp]),
     "jpt_make_level_desc": (ctypes.c_int32, [vp, u64, u64, u32, u32, u32, vp]),
     "jpt_scan_entries": (u32, [u32]),
+    "jpt_query_sizes": (ctypes.c_int32, [vp, u32, vp, u32, u32, vp]),
     "jpt_mark_blocks": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
     "jpt_decode_blocks": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_entropy_decode": (ctypes.c_int32, [vp, vp, vp, vp]),
@@ -196,6 +203,18 @@ def layout(infos: list[LevelInfo]):
     wl = np.zeros(max(1, nb.value // 32), np.uint32)
     _check("jpt_layout", L.jpt_layout(arr, len(infos), _np_ptr(base), _np_ptr(wl), len(wl), ctypes.byref(nb)))
     return base, wl, nb.value
+
+
+def query_sizes(infos: list[LevelInfo], view_sizes, filt: int) -> SizesC:
+    """jpt_query_sizes for a scene's level infos and views given as
+    (width, height) pairs."""
+    arr = (LevelInfo * len(infos))(*infos)
+    vs = (ViewC * max(1, len(view_sizes)))()
+    for i, (w, h) in enumerate(view_sizes):
+        vs[i] = ViewC(None, None, w, h, w, w)
+    out = SizesC()
+    _check("jpt_query_sizes", lib().jpt_query_sizes(arr, len(infos), vs, len(view_sizes), filt, ctypes.byref(out)))
+    return out
 
 
 def _table_key(info: LevelInfo) -> bytes:
@@ -543,12 +562,11 @@ class Renderer:
         self.scene = DeviceScene(self.host, device)
         self.views = Views(gbufs, device)
         self.filter = filt
-        mode = filt & 0xFF
-        taps = 8 if mode == FILTER_TRILINEAR else (1 if mode == FILTER_NEAREST else 4)
-        cap = self.host.n_items_total
-        self.max_items = int(max_items or min(cap, taps * 4 * self.views.n_pixels + 64))
+        self.sizes = query_sizes([l.info for l in self.host.levels], [(g.shape[1], g.shape[0]) for g in gbufs],
+                                 filt)
+        self.max_items = int(max_items or max(1, self.sizes.max_items))
         self.frame = Frame(self.scene, self.max_items)
-        self.cache = Cache(self.scene, int(n_slots or min(self.host.n_blocks, self.max_items)), policy)
+        self.cache = Cache(self.scene, int(n_slots or max(1, self.sizes.max_blocks)), policy)
         self.frame_no = 0
         self.tuning = tuning
         self.idct_mode = idct_mode

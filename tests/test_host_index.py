@@ -220,3 +220,33 @@ def test_predictor_index_on_pil_files_with_optimised_tables():
     b = io.BytesIO()
     Image.fromarray(rgb).save(b, format="JPEG", quality=85, subsampling=2, optimize=True)
     predicted_equals_sequential(b.getvalue())
+
+
+# ---------------------------------------------------------- size queries
+def _info(w, h, smp):
+    inf = jpt.LevelInfo()
+    inf.width, inf.height, inf.sampling = w, h, smp
+    inf.blk_cols, inf.blk_rows = (w + 15) // 16, (h + 15) // 16
+    return inf
+
+
+def test_query_sizes_closed_forms():
+    """jpt_query_sizes against counts worked out by hand: a 256^2 4:2:0
+    texture (256 blocks, one item each), a 40x24 4:4:4 level (3x2 blocks of
+    up to four MCUs each) and block ids padded to multiples of 32."""
+    infos = [_info(256, 256, 420), _info(40, 24, 444)]
+    s = jpt.query_sizes(infos, [(256, 256)], jpt.FILTER_NEAREST)
+    assert s.n_blocks == 256 + 32 and s.vis_words == 9 and s.scan_entries == jpt.lib().jpt_scan_entries(288)
+    assert s.items_total == 256 + 6 * 4 and s.pixels == 65536
+    assert s.max_items == 280 and s.max_blocks == 262 and s.texel_words == 262 * 256
+    assert s.coef_entries == 280 * 6 * 64
+    # few pixels bound the frame instead: 3 pixels, trilinear (8 blocks a pixel, 4 items a 4:4:4 block)
+    s = jpt.query_sizes(infos, [(3, 1)], jpt.FILTER_TRILINEAR)
+    assert s.max_blocks == 24 and s.max_items == 96
+    s = jpt.query_sizes(infos[:1], [(2, 1), (1, 1)], jpt.FILTER_BILINEAR | jpt.FILTER_MIP_OFF)
+    assert s.max_blocks == 12 and s.max_items == 12 and s.pixels == 3
+    s = jpt.query_sizes(infos[:1], [(5, 1)], jpt.FILTER_BILINEAR_CLAMPED)
+    assert s.max_blocks == 5
+    with pytest.raises(jpt.JptError):
+        jpt.query_sizes(infos, [(4, 4)], 9)
+    assert jpt.lib().jpt_query_sizes(None, 0, None, 0, 0, None) == jpt.JPT_E_ARG
