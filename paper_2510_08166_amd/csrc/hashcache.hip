@@ -7,10 +7,11 @@
 // bucket to the decode queue (insertion order), a key already present gets
 // its visibility flag.  The queue becomes the decoder's work list and takes
 // free slots.  Resolve finds every tap's slot by probing the map.  Update
-// Cache evicts every block the frame did not read; here it runs at the start
-// of the next frame: the visible entries keep their slots (recorded per slot
-// in `owner`), the rest free theirs, and the map is rebuilt from the kept
-// entries so that no deleted key breaks a probe chain.
+// Cache evicts every block the frame does not read: after mark, before the
+// new blocks take slots, the entries without the visibility flag free their
+// slots (their keys stay, slotless, so that no probe chain breaks); the
+// next frame starts from a map rebuilt from the kept entries (recorded per
+// slot in `owner`).
 //
 // Limits of the key (those of the paper): at most 65,536 blocks per level
 // (4096^2 texels), 8,191 textures, 8 levels per texture, 4:2:0 levels only
@@ -67,8 +68,17 @@ __global__ __launch_bounds__(kThreads) void k_hash_begin(uint32_t *__restrict__ 
     }
 }
 
-// Evict every entry the last frame did not read (its slot back on the free
-// stack), keep the others in owner[], and empty the map.
+// Empty the map (its kept entries are in owner[]).
+__global__ __launch_bounds__(kThreads) void k_hash_clear(uint32_t *__restrict__ hash, uint32_t n_buckets) {
+    for (uint32_t h = blockIdx.x * kThreads + threadIdx.x; h < n_buckets; h += gridDim.x * kThreads) {
+        hash[2 * h] = kEmpty;
+        hash[2 * h + 1] = 0;
+    }
+}
+
+// Update Cache, after mark: every entry this frame does not read gives its
+// slot back to the free stack (before the new blocks take slots); its key
+// stays in the map without a slot, so no probe chain breaks.
 __global__ __launch_bounds__(kThreads) void k_hash_evict(uint32_t *__restrict__ hash, uint32_t n_buckets,
                                                          uint32_t *__restrict__ owner,
                                                          uint32_t *__restrict__ free_stack, uint32_t n_slots,
@@ -76,14 +86,13 @@ __global__ __launch_bounds__(kThreads) void k_hash_evict(uint32_t *__restrict__ 
     for (uint32_t h = blockIdx.x * kThreads + threadIdx.x; h < n_buckets; h += gridDim.x * kThreads) {
         const uint32_t key = hash[2 * h], val = hash[2 * h + 1];
         const uint32_t slot = val & kSlotMask;
-        // (an entry queued without a slot is visible, so never evicted: it just is not kept)
+        // (an entry queued without a slot is visible, so never evicted)
         if (key != kEmpty && !(val & kVis) && slot < n_slots) {
             owner[slot] = JPT_SLOT_NONE;
             free_stack[atomicAdd(meta + JPT_META_TOP, 1u)] = slot;
             atomicAdd(meta + JPT_META_EVICTED, 1u);
+            hash[2 * h + 1] = kSlotMask;
         }
-        hash[2 * h] = kEmpty;
-        hash[2 * h + 1] = 0;
     }
 }
 
@@ -108,8 +117,8 @@ __global__ __launch_bounds__(kThreads) void k_hash_reinsert(uint32_t *__restrict
 }
 
 // ------------------------------------------------------------------- mark
-// Insert a key; a new one appends its bucket to the queue.  Both a new key
-// and an old one read for the first time this frame count as visible.
+// Insert a key; a new one appends its bucket to the queue.  A key counts
+// as visible once per frame: the thread whose atomicOr sets its flag.
 __device__ __forceinline__ void insert(uint32_t *__restrict__ hash, uint32_t mask, uint32_t key,
                                        uint32_t *__restrict__ queue, uint32_t max_items, uint32_t *__restrict__ meta,
                                        uint32_t *__restrict__ counters) {
@@ -117,8 +126,10 @@ __device__ __forceinline__ void insert(uint32_t *__restrict__ hash, uint32_t mas
     for (uint32_t p = 0; p <= mask; p++) {
         const uint32_t k = atomicCAS(hash + 2 * h, kEmpty, key);
         if (k == kEmpty) {
-            atomicOr(hash + 2 * h + 1, kVis | kSlotMask);  // visible, no slot until the queue gives one
-            atomicAdd(meta + JPT_META_VISIBLE, 1u);
+            // visible, no slot until the queue gives one; a thread that found
+            // the key between the CAS and this may have set the flag first,
+            // and only the one that sets it counts the block
+            if (!(atomicOr(hash + 2 * h + 1, kVis | kSlotMask) & kVis)) atomicAdd(meta + JPT_META_VISIBLE, 1u);
             const uint32_t q = atomicAdd(meta + JPT_META_QCOUNT, 1u);
             if (q < max_items) queue[q] = h;
             return;
@@ -273,8 +284,10 @@ __global__ __launch_bounds__(kThreads) void k_hash_resolve(const jpt_level_desc 
             const uint32_t first = texs[px.tex].first_level;
             uint32_t lvl[2][3] = {{0, 0, 0}, {0, 0, 0}};
             bool missing = false;
-            for (int k = 0; k < nf; k++) {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
                 const LevelFoot &F = foot[k];
+                if (k >= nf || F.lw == 0) continue;  // a level of zero weight was not marked and is not read
                 uint32_t acc[3] = {0, 0, 0};
                 const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
                 const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
@@ -327,8 +340,8 @@ jpt_status hash_mark_frame(const jpt_scene *scene, const jpt_view *views, uint32
                            jpt_frame *frame, jpt_cache *cache, hipStream_t st) {
     const uint32_t mask = cache->n_buckets - 1;
     hipLaunchKernelGGL(k_hash_begin, dim3(1), dim3(kThreads), 0, st, cache->meta, frame->counters);
-    hipLaunchKernelGGL(k_hash_evict, dim3(grid_of(cache->n_buckets, 2048)), dim3(kThreads), 0, st, cache->hash,
-                       cache->n_buckets, cache->owner, cache->free_stack, cache->n_slots, cache->meta);
+    hipLaunchKernelGGL(k_hash_clear, dim3(grid_of(cache->n_buckets, 2048)), dim3(kThreads), 0, st, cache->hash,
+                       cache->n_buckets);
     hipLaunchKernelGGL(k_hash_reinsert, dim3(grid_of(cache->n_slots, 2048)), dim3(kThreads), 0, st, cache->hash, mask,
                        cache->owner, cache->n_slots, frame->counters);
     HIP_CHECK_LAUNCH();
@@ -349,6 +362,8 @@ jpt_status hash_mark_frame(const jpt_scene *scene, const jpt_view *views, uint32
 #undef JPT_HASH_MARK
         HIP_CHECK_LAUNCH();
     }
+    hipLaunchKernelGGL(k_hash_evict, dim3(grid_of(cache->n_buckets, 2048)), dim3(kThreads), 0, st, cache->hash,
+                       cache->n_buckets, cache->owner, cache->free_stack, cache->n_slots, cache->meta);
     hipLaunchKernelGGL(k_hash_queue, dim3(grid_of(frame->max_items, 1024)), dim3(kThreads), 0, st, scene->levels,
                        scene->textures, cache->hash, frame->work, frame->max_items, cache->slot_of, cache->owner,
                        cache->free_stack, cache->meta, frame->counters);
