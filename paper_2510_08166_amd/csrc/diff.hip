@@ -259,12 +259,12 @@ __global__ __launch_bounds__(256) void k_fwd_resolve(const jpt_level_desc *__res
 // the tile in an LDS table keyed by texel (neighbouring pixels share texels),
 // then flushes each touched texel with one global atomic per channel.  All
 // sums are 64-bit fixed point, so the result does not depend on the order.
-constexpr int kAccSize = 2048, kAccProbes = 8, kBwdRows = 4;
+constexpr int kAccLog2 = 11, kAccSize = 1 << kAccLog2, kAccProbes = 8, kBwdRows = 4;
 
 __device__ __forceinline__ void acc_add(uint32_t *s_key, unsigned long long *s_val,
                                         unsigned long long *__restrict__ dtexel, uint32_t addr, long long a0,
                                         long long a1, long long a2) {
-    uint32_t h = (addr * 2654435761u) >> (32 - 11);
+    uint32_t h = (addr * 2654435761u) >> (32 - kAccLog2);
     for (int p = 0; p < kAccProbes; p++) {
         const uint32_t old = atomicCAS(s_key + h, 0xFFFFFFFFu, addr);
         if (old == 0xFFFFFFFFu || old == addr) {
@@ -390,23 +390,45 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
     }
 }
 
-// The largest |dL/dframe| of one view (fp32 bits; non-negative floats order
-// as their bits), max-reduced into counters[JPT_CTR_GRAD_MAX]; a non-finite
-// entry raises JPT_ERR_GRAD.
+// The largest |dL/dframe| over all views (fp32 bits; non-negative floats
+// order as their bits), max-reduced into counters[JPT_CTR_GRAD_MAX]; a
+// non-finite entry raises JPT_ERR_GRAD.  Each thread keeps 8 loads in
+// flight; the workgroup reduces in registers and LDS and makes one atomic
+// (a few hundred workgroups: atomics on one address serialise).
+constexpr int kAbsUnroll = 8;
+constexpr uint32_t kAbsGroups = 256;
 __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, uint64_t n,
                                                 uint32_t *__restrict__ counters) {
+    __shared__ uint32_t s_m[4], s_bad[4];
     uint32_t m = 0;
     bool bad = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-        const float v = fabsf(g[i]);
-        bad |= !(v <= 3.4028234664e38f);
-        m = max(m, __float_as_uint(v));
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += stride * kAbsUnroll) {
+        float v[kAbsUnroll];
+#pragma unroll
+        for (int u = 0; u < kAbsUnroll; u++) {
+            const uint64_t i = i0 + (uint64_t)u * stride;
+            v[u] = i < n ? fabsf(g[i]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kAbsUnroll; u++) {
+            bad |= !(v[u] <= 3.4028234664e38f);
+            m = max(m, __float_as_uint(v[u]));
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    const bool wbad = __ballot(bad) != 0;
     if ((threadIdx.x & 63) == 0) {
-        if (bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_GRAD);
-        if (m) atomicMax(counters + JPT_CTR_GRAD_MAX, bad ? 0u : m);
+        s_m[threadIdx.x >> 6] = m;
+        s_bad[threadIdx.x >> 6] = wbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t bm = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        const bool bb = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
+        if (bb) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_GRAD);
+        if (bm && !bb) atomicMax(counters + JPT_CTR_GRAD_MAX, bm);
     }
 }
 
@@ -503,8 +525,8 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
     size_t total = 0;
     for (uint32_t v = 0; v < n_views; v++) total += (size_t)views[v].width * views[v].height * 3;
     if (total)
-        hipLaunchKernelGGL(k_absmax, dim3((uint32_t)std::min<size_t>((total + 255) / 256, 2048)), dim3(256), 0, st,
-                           dframe, (uint64_t)total, frame->counters);
+        hipLaunchKernelGGL(k_absmax, dim3((uint32_t)std::min<size_t>((total + 2047) / 2048, kAbsGroups)), dim3(256), 0,
+                           st, dframe, (uint64_t)total, frame->counters);
     HIP_CHECK_LAUNCH();
     size_t off = 0;
     for (uint32_t v = 0; v < n_views; v++) {
