@@ -64,7 +64,8 @@ typedef int32_t jpt_status;
 #define JPT_E_RANGE (-4)        /* a value does not fit the index format */
 #define JPT_E_BUFSIZE (-5)      /* caller buffer too small */
 #define JPT_E_HIP (-6)          /* a HIP runtime call failed */
-#define JPT_E_CAPACITY (-7)     /* scene too large for 32-bit block ids */
+#define JPT_E_CAPACITY (-7)     /* scene too large: 32-bit block ids, or the static scratch of
+                                   jpt_mark_blocks_static */
 
 #define JPT_SAMPLING_420 420u
 #define JPT_SAMPLING_444 444u
@@ -400,6 +401,23 @@ uint32_t jpt_scan_entries(uint32_t n_blocks);
  * Errors: JPT_E_ARG (NULL/short buffers, filter, view sizes), JPT_E_HIP. */
 jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                            jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream);
+
+/* jpt_mark_blocks for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and results, but frame->scan is ignored and the scan
+ * scratch is a device array inside the library, JPT_STATIC_SCAN_ENTRIES u64
+ * entries (512 KiB) held by every device the library runs on until the
+ * process ends.  The call allocates nothing; on its first call on a device
+ * (the current device, which must own `stream`) it looks up that device's
+ * copy of the array.  Each call first zeroes the jpt_scan_entries(n_blocks)
+ * entries it uses (a kernel on `stream`, no memset), since the array keeps
+ * the previous call's contents.  Calls that overlap on one device share the
+ * array and race: serialise them (one stream, or events).
+ * Errors: those of jpt_mark_blocks, JPT_E_CAPACITY (jpt_scan_entries(n_blocks)
+ * > JPT_STATIC_SCAN_ENTRIES), JPT_E_HIP (the array's address). */
+#define JPT_STATIC_SCAN_ENTRIES 65536u
+jpt_status jpt_mark_blocks_static(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
+                                  jpt_frame *frame, jpt_cache *cache, const jpt_tuning *tuning, void *stream);
 
 /* Decode (paper: Decode).  For every work item listed by the last
  * jpt_mark_blocks on this frame: entropy-decode the MCU through the index

@@ -11,6 +11,9 @@
 // scan.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "dev_common.h"
 #include "hashcache.h"
 
@@ -941,6 +944,63 @@ extern "C" jpt_status jpt_mark_blocks(const jpt_scene *scene, const jpt_view *vi
     if (s != JPT_OK) return s;
     if (!frame->scan) return JPT_E_ARG;
     return mark_frame(scene, views, n_views, filter, frame, frame->scan, cache, tuning, stream);
+}
+
+// ------------------------------------------------- no-allocation variant
+// jpt_mark_blocks_static keeps the scan scratch in this array instead of
+// frame->scan.  Each device holds its own copy at its own address, found
+// once per device with hipGetSymbolAddress; host code uses only that
+// address, never the array's name (which on the host is a stand-in, not a
+// device address).  Calls that overlap on one device share it and race.
+static __device__ __align__(256) uint64_t scratch[JPT_STATIC_SCAN_ENTRIES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<uint64_t *> g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch` (JPT_E_HIP if it cannot be had).
+jpt_status static_scratch(uint64_t **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return JPT_E_HIP;
+    uint64_t *p = g_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            void *addr = nullptr;
+            if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return JPT_E_HIP;
+            p = static_cast<uint64_t *>(addr);
+            g_scratch[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return JPT_OK;
+}
+
+// Zero n entries (a kernel, not a memset: safe inside a captured graph).
+__global__ __launch_bounds__(256) void k_zero_scan(uint64_t *__restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" jpt_status jpt_mark_blocks_static(const jpt_scene *scene, const jpt_view *views, uint32_t n_views,
+                                             uint32_t filter, jpt_frame *frame, jpt_cache *cache,
+                                             const jpt_tuning *tuning, void *stream) {
+    const jpt_status s = mark_args(scene, views, n_views, filter, frame);
+    if (s != JPT_OK) return s;
+    const uint32_t need = jpt_scan_entries(scene->n_blocks);
+    if (need > JPT_STATIC_SCAN_ENTRIES) return JPT_E_CAPACITY;
+    uint64_t *scan = nullptr;
+    const jpt_status a = static_scratch(&scan);
+    if (a != JPT_OK) return a;
+    // the array keeps the last call's contents: the entries this scene uses
+    // start at zero, as frame->scan does for jpt_mark_blocks
+    hipLaunchKernelGGL(k_zero_scan, dim3(grid_for(need, 256, 256)), dim3(256), 0, (hipStream_t)stream, scan, need);
+    HIP_CHECK_LAUNCH();
+    return mark_frame(scene, views, n_views, filter, frame, scan, cache, tuning, stream);
 }
 
 namespace {

@@ -93,6 +93,7 @@ class SizesC(ctypes.Structure):
 
 LRU_MAX_AGE = 1023
 CACHE_META_WORDS = 16 + LRU_MAX_AGE + 1 + 2048 + 2048 + 1024
+STATIC_SCAN_ENTRIES = 65536
 
 
 class TuningC(ctypes.Structure):
@@ -115,6 +116,7 @@ SIGNATURES = {
     "jpt_scan_entries": (u32, [u32]),
     "jpt_query_sizes": (ctypes.c_int32, [vp, u32, vp, u32, u32, vp]),
     "jpt_mark_blocks": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
+    "jpt_mark_blocks_static": (ctypes.c_int32, [vp, vp, u32, u32, vp, vp, vp, vp]),
     "jpt_decode_blocks": (ctypes.c_int32, [vp, vp, vp, u32, vp, vp]),
     "jpt_entropy_decode": (ctypes.c_int32, [vp, vp, vp, vp]),
     "jpt_decode_reduced": (ctypes.c_int32, [vp, vp, u32, vp, vp, vp]),
@@ -453,6 +455,15 @@ def current_stream():
 def mark_blocks(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Cache | None, tuning=None,
                 stream=None):
     _check("jpt_mark_blocks", lib().jpt_mark_blocks(
+        ctypes.byref(scene.c), views.c, views.n, filt, ctypes.byref(frame.c),
+        ctypes.byref(cache.c) if cache is not None else None, ctypes.byref(tuning) if tuning else None,
+        stream if stream is not None else current_stream()))
+
+
+def mark_blocks_static(scene: DeviceScene, views: Views, filt: int, frame: Frame, cache: Cache | None, tuning=None,
+                       stream=None):
+    """jpt_mark_blocks_static: mark_blocks with the library's own scan scratch (frame.scan unused)."""
+    _check("jpt_mark_blocks_static", lib().jpt_mark_blocks_static(
         ctypes.byref(scene.c), views.c, views.n, filt, ctypes.byref(frame.c),
         ctypes.byref(cache.c) if cache is not None else None, ctypes.byref(tuning) if tuning else None,
         stream if stream is not None else current_stream()))

@@ -171,6 +171,26 @@ def test_device_calls_reject_bad_arguments_without_gpu():
     assert L.jpt_mark_blocks(ctypes.byref(sc), None, 0, 7, ctypes.byref(fr), None, None, None) == jpt.JPT_E_ARG
     assert L.jpt_decode_blocks(ctypes.byref(sc), ctypes.byref(fr), None, 0, None, None) == jpt.JPT_E_ARG
     assert L.jpt_resolve(ctypes.byref(sc), None, 0, 0, None, None, None, None) == jpt.JPT_E_ARG
+    assert L.jpt_mark_blocks_static(None, None, 0, 0, None, None, None, None) == jpt.JPT_E_ARG
+    assert L.jpt_mark_blocks_static(ctypes.byref(sc), None, 0, 7, ctypes.byref(fr), None, None, None) == jpt.JPT_E_ARG
+
+
+def test_static_mark_rejects_scenes_beyond_its_scratch():
+    """jpt_mark_blocks_static checks the scene against its fixed scratch
+    before any device work: the largest scene (2^29 block ids) needs more
+    than JPT_STATIC_SCAN_ENTRIES scan entries."""
+    L = jpt.lib()
+    fake = 0x1000  # never dereferenced: the checks fail first
+    sc = jpt.SceneC(fake, fake, fake, fake, fake, 1, 1, 1, 1, 1 << 29, 0)
+    fr = jpt.FrameC(fake, fake, fake, 0, fake, 1, 0)
+    assert L.jpt_scan_entries(1 << 29) > jpt.STATIC_SCAN_ENTRIES
+    assert L.jpt_mark_blocks_static(ctypes.byref(sc), None, 0, 0, ctypes.byref(fr), None, None, None) == \
+        jpt.JPT_E_CAPACITY
+    # the largest scene it takes: 3 per-tile entries and 16 per 256 tiles, plus one
+    tiles = (1 << 29) // 32 // 256
+    while L.jpt_scan_entries(tiles * 256 * 32) > jpt.STATIC_SCAN_ENTRIES:
+        tiles -= 1
+    assert tiles * 256 * 32 >= 100_000_000  # over 25 G texels of block ids
 
 
 # ------------------------------------------- the predictor index reading
