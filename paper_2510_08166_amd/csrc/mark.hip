@@ -1084,17 +1084,19 @@ jpt_status mark_frame(const jpt_scene *scene, const jpt_view *views, uint32_t n_
     hipLaunchKernelGGL(k_lru_evict, dim3(sg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
                        cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
                        cache->meta, frame->counters, evict_all);
-    const uint32_t dg = grid_for(cache->n_slots, 256, 512);
-    hipLaunchKernelGGL(k_lru_deep1, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                       cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
-    hipLaunchKernelGGL(k_lru_deep2, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
-                       cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
-                       cache->meta);
-    hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
-                       cache->meta);
-    hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
-                       cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
-    HIP_CHECK_LAUNCH();
+    if (!evict_all) {  // (evicting every non-visible block ranks nothing: no exact-age passes, no ties)
+        const uint32_t dg = grid_for(cache->n_slots, 256, 512);
+        hipLaunchKernelGGL(k_lru_deep1, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                           cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
+        hipLaunchKernelGGL(k_lru_deep2, dim3(dg), dim3(256), 0, st, cache->owner, cache->last_used, frame->vis,
+                           cache->n_slots, f, cache->slot_of, cache->resident, cache->free_stack, cache->tie_mask,
+                           cache->meta);
+        hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                           cache->meta);
+        hipLaunchKernelGGL(k_tie_pick, dim3(n_tiles), dim3(kScanThreads), 0, st, cache->tie_mask, n_words, scan2,
+                           cache->owner, cache->slot_of, cache->resident, cache->free_stack, cache->meta);
+        HIP_CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL(k_emit_lru, dim3(n_tiles), dim3(kScanThreads), 0, st, frame->vis, cache->resident,
                        scene->word_level, scene->levels, n_words, scan, n_tiles, frame->work,
                        frame->max_items, cache->slot_of, cache->n_slots, frame->counters, cache->free_stack,
