@@ -393,17 +393,18 @@ __global__ __launch_bounds__(64) void k_bwd_texels(const jpt_level_desc *__restr
 // The largest |dL/dframe| over all views (fp32 bits; non-negative floats
 // order as their bits), max-reduced into counters[JPT_CTR_GRAD_MAX]; a
 // non-finite entry raises JPT_ERR_GRAD.  Each thread keeps 8 loads in
-// flight; the workgroup reduces in registers and LDS and makes one atomic
-// (a few hundred workgroups: atomics on one address serialise).
+// flight; the workgroup (16 waves) reduces in registers and LDS and makes
+// one atomic (at most 256 workgroups: atomics on one address serialise).
 constexpr int kAbsUnroll = 8;
-constexpr uint32_t kAbsGroups = 256;
-__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, uint64_t n,
-                                                uint32_t *__restrict__ counters) {
-    __shared__ uint32_t s_m[4], s_bad[4];
+constexpr uint32_t kAbsGroups = 256, kAbsThreads = 1024;
+__global__ __launch_bounds__(kAbsThreads) void k_absmax(const float *__restrict__ g, uint64_t n,
+                                                        uint32_t *__restrict__ counters) {
+    constexpr int kWaves = kAbsThreads / 64;
+    __shared__ uint32_t s_m[kWaves], s_bad[kWaves];
     uint32_t m = 0;
     bool bad = false;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + threadIdx.x; i0 < n; i0 += stride * kAbsUnroll) {
+    const uint64_t stride = (uint64_t)gridDim.x * kAbsThreads;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kAbsThreads + threadIdx.x; i0 < n; i0 += stride * kAbsUnroll) {
         float v[kAbsUnroll];
 #pragma unroll
         for (int u = 0; u < kAbsUnroll; u++) {
@@ -425,8 +426,11 @@ __global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ g, uin
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t bm = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
-        const bool bb = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
+        uint32_t bm = 0, bb = 0;
+        for (int w = 0; w < kWaves; w++) {
+            bm = max(bm, s_m[w]);
+            bb |= s_bad[w];
+        }
         if (bb) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_GRAD);
         if (bm && !bb) atomicMax(counters + JPT_CTR_GRAD_MAX, bm);
     }
@@ -525,8 +529,8 @@ extern "C" jpt_status jpt_backward(const jpt_scene *scene, const jpt_view *views
     size_t total = 0;
     for (uint32_t v = 0; v < n_views; v++) total += (size_t)views[v].width * views[v].height * 3;
     if (total)
-        hipLaunchKernelGGL(k_absmax, dim3((uint32_t)std::min<size_t>((total + 2047) / 2048, kAbsGroups)), dim3(256), 0,
-                           st, dframe, (uint64_t)total, frame->counters);
+        hipLaunchKernelGGL(k_absmax, dim3((uint32_t)std::min<size_t>((total + 8191) / 8192, kAbsGroups)),
+                           dim3(kAbsThreads), 0, st, dframe, (uint64_t)total, frame->counters);
     HIP_CHECK_LAUNCH();
     size_t off = 0;
     for (uint32_t v = 0; v < n_views; v++) {
