@@ -581,6 +581,51 @@ def heavy_form(args, reps=None):
             "frames_visible_new_evicted": counts}
 
 
+def reduced_form(args, r):
+    """Reduced-resolution decode (paper: Discussion, lower resolutions from the
+    DC and the first ACs instead of stored mip levels) on the 1080p frame's
+    work list: the fused decode of the stored levels against
+    jpt_decode_reduced at scales 1/2, 1/4 and 1/8 over the same MCUs (median
+    GPU ms per launch), and what the stored mip levels cost in bytes.  A
+    level-k block made by reduced decode needs the 4^k level-0 MCUs under it,
+    so its cost per output block is 4^k times the reduced decode's per MCU."""
+    import numpy as np
+    import torch
+    from paper_2510_08166_amd import jpt
+    r.mark()
+    torch.cuda.synchronize()
+    n = int(r.frame.counters_host()[jpt.CTR_ITEMS])
+    out = torch.empty(max(1, n) * 64, dtype=torch.int32, device="cuda")
+
+    def timed(fn, reps=20):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        fn()
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    stored = timed(r.decode)
+    red = {}
+    for sc in (1, 2, 3):
+        red["1/%d" % (1 << sc)] = timed(lambda: jpt.decode_reduced(r.scene, r.frame, sc, out, r.tuning))
+    if r.frame.counters_host()[jpt.CTR_ERROR]:
+        raise SystemExit("reduced decode: device error flags %x" % r.frame.counters_host()[jpt.CTR_ERROR])
+    lv = r.host.levels
+    first = {int(f) for f in r.host.tex_first}  # each texture's level 0
+    total = sum(l.stream.nbytes + l.records.nbytes for l in lv)
+    base = sum(l.stream.nbytes + l.records.nbytes for i, l in enumerate(lv) if i in first)
+    per_mcu = {k: v / max(1, n) for k, v in red.items()}
+    return {"items": n, "stored_levels_decode_ms": round(stored, 4),
+            "reduced_decode_ms": {k: round(v, 4) for k, v in red.items()},
+            "cost_per_output_block_vs_stored": {"level %d" % sc: round((4 ** sc) * per_mcu["1/%d" % (1 << sc)] /
+                                                                        (stored / max(1, n)), 2)
+                                                for sc in (1, 2, 3)},
+            "mip_levels_bytes_fraction": round(1.0 - base / total, 4)}
+
+
 def paper_variants(args, wl, host):
     """The paper's relative comparisons on the 1080p workload (Evaluation:
     Performance, Linear Interpolation): per-phase GPU ms of eager frames for
@@ -883,6 +928,7 @@ def main():
         log("timing the CPU on-demand baseline")
         out["cpu_ondemand_baseline"] = cpu_ondemand_baseline(wl, out["value"])
     if args.workload == "frame1080" and not args.no_extra_forms:
+        out["reduced_decode"] = reduced_form(args, r)
         host = r.host
         del r
         t0 = time.perf_counter()

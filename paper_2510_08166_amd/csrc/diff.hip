@@ -264,7 +264,7 @@ constexpr int kAccLog2 = 11, kAccSize = 1 << kAccLog2, kAccProbes = 8, kBwdRows 
 __device__ __forceinline__ void acc_add(uint32_t *s_key, unsigned long long *s_val,
                                         unsigned long long *__restrict__ dtexel, uint32_t addr, long long a0,
                                         long long a1, long long a2) {
-    uint32_t h = (addr * 2654435761u) >> (32 - kAccLog2);
+    uint32_t h = addr & (kAccSize - 1);
     for (int p = 0; p < kAccProbes; p++) {
         const uint32_t old = atomicCAS(s_key + h, 0xFFFFFFFFu, addr);
         if (old == 0xFFFFFFFFu || old == addr) {
