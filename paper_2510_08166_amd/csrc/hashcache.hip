@@ -143,8 +143,77 @@ __device__ __forceinline__ void insert(uint32_t *__restrict__ hash, uint32_t mas
     atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_CAPACITY);
 }
 
-// One thread per pixel; the wave first drops the keys its left neighbour
-// (the previous pixel of the row) also holds, then probes per pixel.
+// The keys of one pixel's footprint under filter kFilter (kEmpty for unused
+// taps and levels of zero weight); `bad` for a pixel outside the key's limits.
+template <uint32_t kFilter>
+__device__ __forceinline__ int pixel_keys(const jpt_level_desc *__restrict__ levels,
+                                          const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
+                                          const jpt_gpixel &px, bool no_mip, uint32_t *keys, LevelFoot foot[2],
+                                          int &nf, uint32_t &tw, bool &bad) {
+    constexpr int kK = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
+#pragma unroll
+    for (int k = 0; k < kK; k++) keys[k] = kEmpty;
+    const int st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw, no_mip);
+    bad = st == PIX_INVALID;
+    if (st != PIX_VALID) return st;
+    const uint32_t first = texs[px.tex].first_level;
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (k >= nf || foot[k].lw == 0) continue;
+        const LevelFoot &F = foot[k];
+        bad |= levels[F.level].sampling != JPT_SAMPLING_420;
+        if (kFilter == JPT_FILTER_NEAREST) {
+            keys[0] = block_key(F, px.tex, first, F.x0 >> 4, F.y0 >> 4);
+            bad |= keys[0] == kEmpty;
+        } else {
+            const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
+            const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int a = 0; a < 2; a++) {
+                    if (wx[a] * wy[b] == 0) continue;
+                    const uint32_t key = block_key(F, px.tex, first, xs[a] >> 4, ys[b] >> 4);
+                    bad |= key == kEmpty;
+                    keys[4 * k + 2 * b + a] = key;
+                }
+        }
+    }
+    return st;
+}
+
+// A workgroup's LDS set of the distinct keys its pixel tile reads (open
+// addressing, linear probing); false when the key finds no room.
+constexpr int kTileSet = 1024, kTileProbes = 16;
+__device__ __forceinline__ bool tile_set_insert(uint32_t *s_keys, uint32_t key) {
+    uint32_t h = (key * 2654435761u) >> 22;  // 10 bits
+#pragma unroll 1
+    for (int p = 0; p < kTileProbes; p++) {
+        const uint32_t old = atomicCAS(s_keys + h, kEmpty, key);
+        if (old == kEmpty || old == key) return true;
+        h = (h + 1) & (kTileSet - 1);
+    }
+    return false;
+}
+// The LDS set's entry of a key, or -1.
+__device__ __forceinline__ int tile_set_find(const uint32_t *s_keys, uint32_t key) {
+    uint32_t h = (key * 2654435761u) >> 22;
+#pragma unroll 1
+    for (int p = 0; p < kTileProbes; p++) {
+        const uint32_t k = s_keys[h];
+        if (k == key) return (int)h;
+        if (k == kEmpty) return -1;
+        h = (h + 1) & (kTileSet - 1);
+    }
+    return -1;
+}
+
+// Mark: the paper inserts every pixel's keys into the map with atomicCAS.
+// Here a workgroup first gathers the distinct keys of its 64 x 16 pixel tile
+// in LDS (the wave drops the keys its left neighbour, the previous pixel of
+// the row, also holds), then inserts each once; the map, its flags and the
+// queue's contents are the same, only the redundant global atomics go.  A
+// key that finds no room in the LDS set goes to the map directly.
 template <uint32_t kFilter>
 __global__ __launch_bounds__(kThreads) void k_hash_mark(const jpt_level_desc *__restrict__ levels,
                                                         const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
@@ -154,46 +223,25 @@ __global__ __launch_bounds__(kThreads) void k_hash_mark(const jpt_level_desc *__
                                                         uint32_t max_items, uint32_t *__restrict__ meta,
                                                         uint32_t *__restrict__ counters) {
     constexpr int kK = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
+    __shared__ uint32_t s_keys[kTileSet];
+    __shared__ uint32_t s_bad;
+    for (int i = threadIdx.x; i < kTileSet; i += kThreads) s_keys[i] = kEmpty;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t x = blockIdx.x * kTileW + lane;
     const uint32_t y = blockIdx.y * kTileH + (threadIdx.x >> 6);
+    bool any_bad = false;
     for (uint32_t yy = y; yy < min(H, blockIdx.y * kTileH + kTileH); yy += kThreads / 64) {
         const jpt_gpixel px = x < W ? gbuf[(size_t)yy * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+        uint32_t keys[kK];
         LevelFoot foot[2];
         int nf;
         uint32_t tw;
-        const int st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw, no_mip);
-        uint32_t keys[kK];
-        bool bad = st == PIX_INVALID;
-#pragma unroll
-        for (int k = 0; k < kK; k++) keys[k] = kEmpty;
-        if (st == PIX_VALID) {
-            const uint32_t first = texs[px.tex].first_level;
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                if (k >= nf || foot[k].lw == 0) continue;
-                const LevelFoot &F = foot[k];
-                bad |= levels[F.level].sampling != JPT_SAMPLING_420;
-                if (kFilter == JPT_FILTER_NEAREST) {
-                    keys[0] = block_key(F, px.tex, first, F.x0 >> 4, F.y0 >> 4);
-                    bad |= keys[0] == kEmpty;
-                } else {
-                    const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
-                    const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
-#pragma unroll
-                    for (int b = 0; b < 2; b++)
-#pragma unroll
-                        for (int a = 0; a < 2; a++) {
-                            if (wx[a] * wy[b] == 0) continue;
-                            const uint32_t key = block_key(F, px.tex, first, xs[a] >> 4, ys[b] >> 4);
-                            bad |= key == kEmpty;
-                            keys[4 * k + 2 * b + a] = key;
-                        }
-                }
-            }
-        }
+        bool bad;
+        pixel_keys<kFilter>(levels, texs, n_tex, px, no_mip, keys, foot, nf, tw, bad);
         if (bad) {
-            atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
+            any_bad = true;
 #pragma unroll
             for (int k = 0; k < kK; k++) keys[k] = kEmpty;
         }
@@ -210,9 +258,15 @@ __global__ __launch_bounds__(kThreads) void k_hash_mark(const jpt_level_desc *__
             for (int j = 0; j < kK; j++) dup |= left[j] == keys[k];
 #pragma unroll
             for (int j = 0; j < k; j++) dup |= keys[j] == keys[k];
-            if (!dup) insert(hash, mask, keys[k], queue, max_items, meta, counters);
+            if (!dup && !tile_set_insert(s_keys, keys[k]))
+                insert(hash, mask, keys[k], queue, max_items, meta, counters);
         }
     }
+    if (__ballot(any_bad) && lane == 0) atomicOr(&s_bad, 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTileSet; i += kThreads)
+        if (s_keys[i] != kEmpty) insert(hash, mask, s_keys[i], queue, max_items, meta, counters);
+    if (threadIdx.x == 0 && s_bad) atomicOr(counters + JPT_CTR_ERROR, JPT_ERR_PIXEL);
 }
 
 // The queue (buckets in insertion order) becomes the work list: each new
@@ -258,6 +312,10 @@ __global__ void k_hash_finish(uint32_t *__restrict__ meta, uint32_t *__restrict_
 }
 
 // ---------------------------------------------------------------- resolve
+// Resolve: the paper probes the map for every tap.  Here a workgroup probes
+// it once per distinct key of its 64 x 16 pixel tile (gathered in LDS as in
+// mark), and each tap then finds its key's slot in the LDS set (a tap whose
+// key found no room there probes the map itself).
 template <uint32_t kFilter>
 __global__ __launch_bounds__(kThreads) void k_hash_resolve(const jpt_level_desc *__restrict__ levels,
                                                            const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
@@ -266,22 +324,67 @@ __global__ __launch_bounds__(kThreads) void k_hash_resolve(const jpt_level_desc 
                                                            uint32_t frame_pitch, bool no_mip,
                                                            const uint32_t *__restrict__ hash, uint32_t mask,
                                                            const uint32_t *__restrict__ texels) {
-    const uint32_t x = blockIdx.x * kTileW + (threadIdx.x & 63);
-    for (uint32_t y = blockIdx.y * kTileH + (threadIdx.x >> 6); y < min(H, blockIdx.y * kTileH + kTileH);
-         y += kThreads / 64) {
-        if (x >= W) continue;
-        const jpt_gpixel px = gbuf[(size_t)y * pitch + x];
+    constexpr int kK = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
+    constexpr int kRows = kTileH / (kThreads / 64);
+    __shared__ uint32_t s_keys[kTileSet];
+    __shared__ uint32_t s_slot[kTileSet];
+    for (int i = threadIdx.x; i < kTileSet; i += kThreads) s_keys[i] = kEmpty;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t x = blockIdx.x * kTileW + lane;
+    const uint32_t y0 = blockIdx.y * kTileH + (threadIdx.x >> 6);
+    jpt_gpixel px[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+        const uint32_t y = y0 + r * (kThreads / 64);
+        px[r] = x < W && y < H ? gbuf[(size_t)y * pitch + x] : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
+    }
+    // the tile's distinct keys
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+        uint32_t keys[kK];
         LevelFoot foot[2];
         int nf;
         uint32_t tw;
-        const int st = pixel_footprint(GlobalDesc{levels, texs}, n_tex, px, kFilter, foot, nf, tw, no_mip);
+        bool bad;
+        pixel_keys<kFilter>(levels, texs, n_tex, px[r], no_mip, keys, foot, nf, tw, bad);
+        uint32_t left[kK];
+#pragma unroll
+        for (int k = 0; k < kK; k++) {
+            left[k] = __shfl_up(keys[k], 1, 64);
+            if (lane == 0) left[k] = kEmpty;
+        }
+#pragma unroll
+        for (int k = 0; k < kK; k++) {
+            bool dup = keys[k] == kEmpty;
+#pragma unroll
+            for (int j = 0; j < kK; j++) dup |= left[j] == keys[k];
+            if (!dup) tile_set_insert(s_keys, keys[k]);
+        }
+    }
+    __syncthreads();
+    // one probe of the map per distinct key
+    for (int i = threadIdx.x; i < kTileSet; i += kThreads) {
+        const uint32_t key = s_keys[i];
+        if (key != kEmpty) s_slot[i] = lookup(hash, mask, key);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRows; r++) {
+        const uint32_t y = y0 + r * (kThreads / 64);
+        if (x >= W || y >= H) continue;
+        uint32_t keys[kK];
+        LevelFoot foot[2];
+        int nf;
+        uint32_t tw;
+        bool bad;
+        const int st = pixel_keys<kFilter>(levels, texs, n_tex, px[r], no_mip, keys, foot, nf, tw, bad);
         uint32_t out;
         if (st == PIX_BACKGROUND) {
             out = 0;
-        } else if (st == PIX_INVALID) {
+        } else if (st == PIX_INVALID || bad) {
             out = JPT_TEXEL_INVALID;
         } else {
-            const uint32_t first = texs[px.tex].first_level;
             uint32_t lvl[2][3] = {{0, 0, 0}, {0, 0, 0}};
             bool missing = false;
 #pragma unroll
@@ -292,12 +395,16 @@ __global__ __launch_bounds__(kThreads) void k_hash_resolve(const jpt_level_desc 
                 const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
                 const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
                 const int na = kFilter == JPT_FILTER_NEAREST ? 1 : 2;
+#pragma unroll
                 for (int b = 0; b < na; b++)
+#pragma unroll
                     for (int a = 0; a < na; a++) {
                         const uint32_t w = kFilter == JPT_FILTER_NEAREST ? 65536u : wx[a] * wy[b];
                         if (w == 0) continue;
-                        // one probe of the map per tap (the paper's cost of linear filtering)
-                        const uint32_t slot = lookup(hash, mask, block_key(F, px.tex, first, xs[a] >> 4, ys[b] >> 4));
+                        const uint32_t key = keys[kFilter == JPT_FILTER_NEAREST ? 0 : 4 * k + 2 * b + a];
+                        // one lookup per tap (the paper's cost of linear filtering), in the tile's set
+                        const int e = tile_set_find(s_keys, key);
+                        const uint32_t slot = e >= 0 ? s_slot[e] : lookup(hash, mask, key);
                         if (slot == JPT_SLOT_NONE) {
                             missing = true;
                             continue;
