@@ -378,7 +378,7 @@ def time_repeated(r, phase, reps=60):
     return e0.elapsed_time(e1) / reps
 
 
-IDCT_MODES = {"fused": 2, "mfma": 0, "scalar": 1}
+IDCT_MODES = {"fused": 2, "mfma": 0, "mfma_bf16": 3, "scalar": 1}
 
 
 def plain_form(args, wl, label, policy=0, n_slots=None):
@@ -837,7 +837,8 @@ def batched_extras(args, r, out):
     n_new = min(int(r.frame.counters_host()[jpt.CTR_NEW]), r.cache.n_slots)
     tex_mfma = r.cache.texels[: n_new * 256].clone()
     times = {}
-    for mode, name in ((jpt.IDCT_MFMA_F16, "mfma_f16"), (jpt.IDCT_SCALAR_F32, "scalar_f32")):
+    for mode, name in ((jpt.IDCT_MFMA_F16, "mfma_f16"), (jpt.IDCT_MFMA_BF16, "mfma_bf16"),
+                       (jpt.IDCT_SCALAR_F32, "scalar_f32")):
         r.idct_mode = mode
         _, med = time_phases(r, args.steps)
         times[name] = round(float(med[2]), 4)
@@ -882,8 +883,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="batched16 only: skip the launch-knob tuner and the MFMA/scalar IDCT comparison")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--idct", default="fused", choices=["fused", "mfma", "scalar"],
-                    help="decode kernels: fused entropy+IDCT+colour, or entropy then the MFMA / scalar IDCT")
+    ap.add_argument("--idct", default="fused", choices=sorted(IDCT_MODES),
+                    help="decode kernels: fused entropy+IDCT+colour, or entropy then the MFMA (fp16, bf16) or scalar IDCT")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is single-GPU (each device would run the same per-frame "

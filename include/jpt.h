@@ -97,6 +97,8 @@ typedef int32_t jpt_status;
 #define JPT_IDCT_FUSED_F32 2u   /* jpt_decode_blocks only: the entropy decoder's wavefront runs the
                                    JPT_IDCT_SCALAR_F32 arithmetic on its own MCU and stores the
                                    texels; frame->coef is not written */
+#define JPT_IDCT_MFMA_BF16 3u   /* the JPT_IDCT_MFMA_F16 contraction with bf16 operands: the basis in
+                                   three bf16 parts, coefficients in exact base-128 digits */
 
 /* counters[] (u32) of a frame */
 #define JPT_CTR_ITEMS 0         /* work items listed this frame (<= max_items) */

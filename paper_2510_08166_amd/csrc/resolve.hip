@@ -25,8 +25,12 @@ struct FilterTraits {
     static constexpr int kTaps = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
 };
 
-// Taps of one pixel: block id, texel offset inside the block's slot and
-// weight (0 = unused tap).  Weights of one level sum to 65536.
+// Taps of one pixel: block id, byte offset of the texel inside its block's
+// slot (row-major 16 x 16 RGBA8) and weight; weights of one level sum to
+// 65536.  Every lane computes all of them without branches: the footprint's
+// texel coordinates lie inside a real level even for background and invalid
+// pixels (whose descriptor indices and coordinates are clamped), so each block id
+// is a valid index; the taps a pixel does not read get weight 0.
 template <int kTaps>
 struct Taps {
     uint32_t blk[kTaps], off[kTaps], w[kTaps];
@@ -37,20 +41,22 @@ __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const j
                                           Taps<FilterTraits<kFilter>::kTaps> &T, uint32_t &tw, int &nf,
                                           bool no_mip) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
-#pragma unroll
-    for (int t = 0; t < kTaps; t++) { T.blk[t] = 0; T.off[t] = 0; T.w[t] = 0; }
     LevelFoot foot[2];
     const int st = pixel_footprint(D, n_tex, px, kFilter, foot, nf, tw, no_mip);
-    if (st != PIX_VALID) return st;
+    if (n_tex == 0) {  // (uniform: the footprint is not filled in)
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-        if (kFilter != JPT_FILTER_TRILINEAR && k > 0) break;
-        if (k >= nf || foot[k].lw == 0) continue;
+        for (int t = 0; t < kTaps; t++) { T.blk[t] = 0; T.off[t] = 0; T.w[t] = 0; }
+        return st;
+    }
+    const bool valid = st == PIX_VALID;
+#pragma unroll
+    for (int k = 0; k < (kFilter == JPT_FILTER_TRILINEAR ? 2 : 1); k++) {
         const LevelFoot &F = foot[k];
+        const bool used = valid && k < nf && F.lw != 0;
         if (kFilter == JPT_FILTER_NEAREST) {
             T.blk[0] = block_of(F, F.x0, F.y0);
-            T.off[0] = (F.y0 & 15) * 16 + (F.x0 & 15);
-            T.w[0] = 65536;
+            T.off[0] = ((F.y0 & 15) << 6) | ((F.x0 & 15) << 2);
+            T.w[0] = used ? 65536u : 0u;
         } else {
             const uint32_t wx[2] = {256 - F.fx, F.fx}, wy[2] = {256 - F.fy, F.fy};
             const uint32_t xs[2] = {F.x0, F.x1}, ys[2] = {F.y0, F.y1};
@@ -60,20 +66,69 @@ __device__ __forceinline__ int pixel_taps(const Desc &D, uint32_t n_tex, const j
                 for (int a = 0; a < 2; a++) {
                     const int t = 4 * k + 2 * b + a;
                     T.blk[t] = block_of(F, xs[a], ys[b]);
-                    T.off[t] = (ys[b] & 15) * 16 + (xs[a] & 15);
-                    T.w[t] = __umul24(wx[a], wy[b]);  // <= 2^16
+                    T.off[t] = ((ys[b] & 15) << 6) | ((xs[a] & 15) << 2);
+                    T.w[t] = used ? __umul24(wx[a], wy[b]) : 0u;  // <= 2^16
                 }
         }
     }
-    return PIX_VALID;
+    return st;
 }
 
-template <uint32_t kFilter, int kDesc>
+// base[byte_off / 4]: a 32-bit offset from a base held in scalar registers
+// (the address is computed by the load unit, no 64-bit arithmetic per lane)
+__device__ __forceinline__ uint32_t load_at(const uint32_t *__restrict__ base, uint32_t byte_off) {
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Texel at byte offset `off` of cache slot `slot`: with kNarrow (every slot
+// within the first 4 GiB of texels) through a 32-bit offset.
+template <bool kNarrow>
+__device__ __forceinline__ uint32_t load_texel(const uint32_t *__restrict__ texels, uint32_t slot, uint32_t off) {
+    if constexpr (kNarrow) return load_at(texels, (slot << 10) | off);
+    else return load_at(texels + (size_t)slot * 256, off);
+}
+
+// Two neighbouring texels of a block row: one 8-byte load (multi-dword
+// global loads need only 4-byte alignment).
+typedef uint32_t TexelPair __attribute__((ext_vector_type(2)));
+typedef TexelPair TexelPairA4 __attribute__((aligned(4)));
+template <bool kNarrow>
+__device__ __forceinline__ TexelPair load_pair(const uint32_t *__restrict__ texels, uint32_t slot, uint32_t off) {
+    const char *p = reinterpret_cast<const char *>(kNarrow ? texels : texels + (size_t)slot * 256);
+    return *reinterpret_cast<const TexelPairA4 *>(p + (kNarrow ? (slot << 10) | off : off));
+}
+
+// Slots and texels of a level's four linear taps k0 ... k0 + 3, at
+// (x0,y0), (x1,y0), (x0,y1), (x1,y1).  x1 usually follows x0 in the same
+// block row: then one 8-byte load per row fetches both (at x0 - 1 when x0 is
+// the block's last column, so that the pair stays inside the block row); a
+// lane whose x1 does not follow x0 (another block, the wrap at the level's
+// edge, a clamped tap) loads it on its own.
+template <bool kNarrow, int k0, int kTaps>
+__device__ __forceinline__ void fetch_linear(const uint32_t *__restrict__ slot_of, const uint32_t *__restrict__ texels,
+                                             uint32_t last_slot, const Taps<kTaps> &T, uint32_t (&slot)[kTaps],
+                                             uint32_t (&tex)[kTaps]) {
+#pragma unroll
+    for (int t = k0; t < k0 + 4; t++) slot[t] = load_at(slot_of, T.blk[t] << 2);
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+        const int t0 = k0 + 2 * b, t1 = t0 + 1;
+        const uint32_t o0 = T.off[t0], o1 = T.off[t1];
+        const bool end = (o0 & 0x3Cu) == 0x3Cu;                   // x0 & 15 == 15
+        const bool next = T.blk[t1] == T.blk[t0] && o1 == o0 + 4u;  // x1 = x0 + 1 in the same block row
+        const TexelPair pr = load_pair<kNarrow>(texels, min(slot[t0], last_slot), end ? o0 - 4u : o0);
+        tex[t0] = end ? pr.y : pr.x;
+        tex[t1] = next ? pr.y : load_texel<kNarrow>(texels, min(slot[t1], last_slot), o1);
+    }
+}
+
+template <uint32_t kFilter, int kDesc, bool kNarrow>
 __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__restrict__ levels,
                                                       const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                       uint32_t n_lev, const ViewTable tab,
                                                       const uint32_t *__restrict__ slot_of,
-                                                      const uint32_t *__restrict__ texels, bool no_mip) {
+                                                      const uint32_t *__restrict__ texels, uint32_t last_slot,
+                                                      bool no_mip) {
     constexpr int kTaps = FilterTraits<kFilter>::kTaps;
     __shared__ TexRec s_t[kDesc != DESC_HBM ? kLdsTexCap : 1];
     __shared__ LevRec s_l[kDesc == DESC_LDS ? kLdsLevCap : 1];
@@ -108,14 +163,19 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
             else if constexpr (kDesc == DESC_TEX_LDS)
                 st = pixel_taps<kFilter>(MixDesc{s_t, levels}, n_tex, px[r], T, tw, nf, no_mip);
             else st = pixel_taps<kFilter>(GlobalDesc{levels, texs}, n_tex, px[r], T, tw, nf, no_mip);
-            // all slot lookups of the pixel, then all texel loads
-            // unused taps read block 0 / slot 0 (valid addresses) and get weight 0
+            // the pixel's slot lookups, then its texel loads (block ids are
+            // below 2^29, so their byte offsets fit 32 bits; a block in no slot
+            // reads the last slot, a valid address, and matters only if its
+            // weight is not 0)
             uint32_t slot[kTaps], tex[kTaps];
+            if constexpr (kTaps == 4) {
+                fetch_linear<kNarrow, 0>(slot_of, texels, last_slot, T, slot, tex);
+            } else {  // (trilinear: the paired form of both levels spills registers)
 #pragma unroll
-            for (int t = 0; t < kTaps; t++) slot[t] = slot_of[T.blk[t]];
+                for (int t = 0; t < kTaps; t++) slot[t] = load_at(slot_of, T.blk[t] << 2);
 #pragma unroll
-            for (int t = 0; t < kTaps; t++)
-                tex[t] = texels[(size_t)(slot[t] != JPT_SLOT_NONE ? slot[t] : 0u) * 256 + T.off[t]];
+                for (int t = 0; t < kTaps; t++) tex[t] = load_texel<kNarrow>(texels, min(slot[t], last_slot), T.off[t]);
+            }
             if (x >= W || y >= H) continue;
             uint32_t out;
             if (st == PIX_BACKGROUND) {
@@ -161,12 +221,19 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
     }
 }
 
+// kNarrow: every texel of the cache within 4 GiB of its base (at most 2^22
+// slots of 1 KiB)
 template <uint32_t kFilter, int kDesc>
 void launch_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, const jpt_cache *cache,
                  bool no_mip, hipStream_t st) {
-    hipLaunchKernelGGL((k_resolve<kFilter, kDesc>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
-                       scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels,
-                       no_mip);
+    if (cache->n_slots <= (1u << 22))
+        hipLaunchKernelGGL((k_resolve<kFilter, kDesc, true>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels,
+                           cache->n_slots - 1, no_mip);
+    else
+        hipLaunchKernelGGL((k_resolve<kFilter, kDesc, false>), dim3(groups), dim3(kThreads), 0, st, scene->levels,
+                           scene->textures, scene->n_textures, scene->n_levels, tab, cache->slot_of, cache->texels,
+                           cache->n_slots - 1, no_mip);
 }
 
 template <uint32_t kFilter>

@@ -28,7 +28,7 @@ FILTER_MIP_OFF = 0x100
 CACHE_NONE, CACHE_LRU, CACHE_EVICT_INVISIBLE, CACHE_HASH = 0, 1, 2, 3
 INDEX_SPLICED, INDEX_PREDICTORS = 0, 1
 SCENE_PREDICTOR_INDEX = 1
-IDCT_MFMA_F16, IDCT_SCALAR_F32, IDCT_FUSED_F32 = 0, 1, 2
+IDCT_MFMA_F16, IDCT_SCALAR_F32, IDCT_FUSED_F32, IDCT_MFMA_BF16 = 0, 1, 2, 3
 FRAME_AUTO = 0xFFFFFFFF
 TUNE_XCD_TILES = 1
 CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT, CTR_GRAD_MAX = range(8)

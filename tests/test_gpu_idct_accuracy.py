@@ -20,6 +20,9 @@ from paper_2510_08166_amd import synth
 
 pytestmark = pytest.mark.gpu
 
+# JPT_IDCT_* of the 8-bit paths
+MODES = {"mfma_f16": 0, "scalar_f32": 1, "mfma_bf16": 3}
+
 
 def fdct_matrix():
     x = np.arange(8)[:, None]
@@ -145,7 +148,7 @@ def test_ieee1180_float_path_full_ranges(gpu, lo, hi, sign):
     assert st["blocks"] >= 10000 and within_bounds(st)
 
 
-@pytest.mark.parametrize("mode_name", ["mfma_f16", "scalar_f32", "float"])
+@pytest.mark.parametrize("mode_name", ["mfma_f16", "mfma_bf16", "scalar_f32", "float"])
 def test_ieee1180_zero_in_zero_out(gpu, mode_name):
     """All-zero coefficients give exactly zero samples (texels of 128 on the
     8-bit paths, float texels of exactly 128.0)."""
@@ -161,17 +164,16 @@ def test_ieee1180_zero_in_zero_out(gpu, mode_name):
         assert (diff.texel_f[: n * 768].cpu().numpy() == 128.0).all()
         return
     r.frame.coef[: n * 384].zero_()
-    jpt.idct_color(r.scene, r.frame, r.cache, jpt.IDCT_MFMA_F16 if mode_name == "mfma_f16" else jpt.IDCT_SCALAR_F32)
+    jpt.idct_color(r.scene, r.frame, r.cache, MODES[mode_name])
     torch.cuda.synchronize()
     t = r.cache.texels[: n * 256].cpu().numpy().view(np.uint8).reshape(-1, 4)
     assert (t[:, :3] == 128).all()
 
 
 @pytest.mark.parametrize("L", [5, 100])
-@pytest.mark.parametrize("mode_name", ["mfma_f16", "scalar_f32"])
+@pytest.mark.parametrize("mode_name", ["mfma_f16", "mfma_bf16", "scalar_f32"])
 def test_ieee1180_style(gpu, L, mode_name):
-    from paper_2510_08166_amd import jpt
-    mode = jpt.IDCT_MFMA_F16 if mode_name == "mfma_f16" else jpt.IDCT_SCALAR_F32
+    mode = MODES[mode_name]
     st = run_case(L, mode, seed=40 + L)
     print("IDCT %s L=%d: %s" % (mode_name, L, st), flush=True)
     assert st["peak"] <= 1 and st["pmse"] <= 0.06 and st["omse"] <= 0.02

@@ -62,6 +62,17 @@ def test_scalar_f32_idct(gpu, case):
     full_parity(wl, idct_mode=jpt.IDCT_SCALAR_F32)
 
 
+@pytest.mark.parametrize("case", ["420 trilinear", "444 ragged"])
+def test_mfma_bf16_idct(gpu, case):
+    """The bf16 MFMA IDCT (JPT_IDCT_MFMA_BF16) to the same bar as the fp16 one."""
+    from paper_2510_08166_amd import jpt
+    if case == "444 ragged":
+        wl = configs.quad_scene(23, 3, 200, 50, 95, 4, 160, 120, 12, sampling=444, filt=configs.FILTER_BILINEAR)
+    else:
+        wl = configs.reduced(seed=13, filt=configs.FILTER_TRILINEAR)
+    full_parity(wl, idct_mode=jpt.IDCT_MFMA_BF16)
+
+
 @pytest.mark.parametrize("case", ["420 trilinear", "444 ragged", "corrupt", "8 decode groups", "16 decode groups"])
 def test_fused_decode_matches_scalar(gpu, case):
     """JPT_IDCT_FUSED_F32 (entropy decode, IDCT and colour in one kernel) stores
@@ -307,12 +318,12 @@ def test_lru_exact_ages_past_the_histogram_cap(gpu):
 
 @pytest.mark.parametrize("sampling", [420, 444])
 @pytest.mark.parametrize("q,dc_max,density", [(8, 255, 0.05), (255, 2047, 0.1)])
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_wide_coefficients(gpu, sampling, q, dc_max, density, mode):
     """Crafted streams at the limits the index admits (ACs up to 1023, DCs
     up to 2047, quantisers up to 255, so |F| up to 521985): coefficients
     bit-exact and texels within 1 LSB in every IDCT mode; the MFMA path
-    takes its three-digit split of F for these units."""
+    takes its three-digit split of F for these units (fp16 and bf16)."""
     from paper_2510_08166_amd.synth import EncodedTexture, GPIXEL_DTYPE
     from jpeg_writer import mcu_count, mcus_from_coefs, random_coefs, write_jpeg
     w, h = (40, 24) if sampling == 420 else (24, 40)
