@@ -19,7 +19,9 @@
 
 namespace {
 
-constexpr int kMarkThreads = 256;  // 4 waves per workgroup
+// Workgroup sizes of the mark kernel: 4 waves (8 rows of a tile each) or 8
+// waves (4 rows each); see launch_mark_desc.
+constexpr int kMarkThreads = 256, kMarkThreadsWide = 512;
 
 // (LRU frames) the bitmask, the counters, the eviction's tie mask, age
 // histograms, evicted count and deep-selection flag
@@ -90,15 +92,16 @@ __device__ __forceinline__ void add_count(uint64_t *__restrict__ cnt, uint64_t *
               (unsigned long long)packed);
 }
 
+template <int kThreads>
 __device__ __forceinline__ void flush_set(const uint32_t *s_key, const uint32_t *s_bits, uint32_t *s_ctile,
                                           unsigned long long *s_cval, uint32_t *__restrict__ vis,
                                           const TileCounts &tc) {
-    constexpr int kPer = kSetSize / kMarkThreads;
+    constexpr int kPer = kSetSize / kThreads;
     uint32_t key[kPer], bits[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
-        key[j] = s_key[threadIdx.x + j * kMarkThreads];
-        bits[j] = s_bits[threadIdx.x + j * kMarkThreads];
+        key[j] = s_key[threadIdx.x + j * kThreads];
+        bits[j] = s_bits[threadIdx.x + j * kThreads];
     }
     if (!tc.cnt) {
 #pragma unroll
@@ -159,13 +162,13 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
 // neighbour (the previous pixel of the row) also touches, and inserts the
 // rest into the tile's LDS set; the set is flushed to the bitmask with one
 // HBM atomic per distinct word (and, with counts, one per tile level).
-template <uint32_t kFilter, int kDesc>
-__global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
+template <uint32_t kFilter, int kDesc, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                        uint32_t n_lev, const ViewTable tab,
                                                        uint32_t *__restrict__ vis, const TileCounts tc,
                                                        uint32_t *__restrict__ err_word, bool no_mip) {
-    constexpr int kRows = kTileH / (kMarkThreads / 64);  // rows per wave
+    constexpr int kRows = kTileH / (kThreads / 64);  // rows per wave
     constexpr int kIds = kFilter == JPT_FILTER_NEAREST ? 1 : (kFilter == JPT_FILTER_TRILINEAR ? 8 : 4);
     __shared__ uint32_t s_key[kSetSize], s_bits[kSetSize], s_ctile[kCntSlots];
     __shared__ unsigned long long s_cval[kCntSlots];
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
             return (x < W && y < H) ? g : jpt_gpixel{0.f, 0.f, JPT_TEX_BACKGROUND, 0.f};
         };
         jpt_gpixel nxt = load_px(y0);
-        for (int i = threadIdx.x; i < kSetSize; i += kMarkThreads) {
+        for (int i = threadIdx.x; i < kSetSize; i += kThreads) {
             s_key[i] = 0xFFFFFFFFu;
             s_bits[i] = 0;
         }
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
 #pragma unroll 1
         for (int r = 0; r < kRows; r++) {
             const jpt_gpixel px = nxt;
-            if (r + 1 < kRows) nxt = load_px(y0 + (r + 1) * (kMarkThreads / 64));
+            if (r + 1 < kRows) nxt = load_px(y0 + (r + 1) * (kThreads / 64));
             uint32_t ids[kIds];
 #pragma unroll
             for (int k = 0; k < kIds; k++) ids[k] = 0xFFFFFFFFu;
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
             }
         }
         __syncthreads();
-        flush_set(s_key, s_bits, s_ctile, s_cval, vis, tc);
+        flush_set<kThreads>(s_key, s_bits, s_ctile, s_cval, vis, tc);
         __syncthreads();  // the set is reused by the next tile
     }
     if (__ballot(invalid) && lane == 0) atomicOr(&s_bad, 1u);
@@ -269,11 +272,44 @@ __global__ __launch_bounds__(kMarkThreads) void k_mark(const jpt_level_desc *__r
     if (threadIdx.x == 0 && s_bad) atomicOr(err_word, JPT_ERR_PIXEL);
 }
 
+// Workgroups of the 8-wave mark the GPU holds at once (compute units x
+// resident workgroups per unit), queried once per device.
+template <uint32_t kFilter, int kDesc>
+uint32_t wide_mark_capacity() {
+    constexpr int kMaxDev = 64;
+    static std::atomic<uint32_t> known[kMaxDev];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 0u;
+    uint32_t g = known[dev].load(std::memory_order_relaxed);
+    if (g) return g;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mark<kFilter, kDesc, kMarkThreadsWide>,
+                                                     kMarkThreadsWide, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+        cus <= 0)
+        return 0u;
+    g = (uint32_t)per_cu * (uint32_t)cus;
+    known[dev].store(g, std::memory_order_relaxed);
+    return g;
+}
+
+// A launch of at most two rounds of 8-wave workgroups takes 8 waves per
+// tile: the tiles' rows are walked by twice the waves, each with half the
+// serial chain of loads and set inserts (a 1080p frame, 1,020 tiles: 16.5
+// against 18.0 us).  A longer launch, where the next round keeps the GPU
+// full anyway, takes 4, whose tiles cost fewer barrier waits (16 views,
+// 42,000 tiles: 235 against 265 us with 8).
 template <uint32_t kFilter, int kDesc>
 void launch_mark_desc(const jpt_scene *scene, const ViewTable &tab, uint32_t groups, jpt_frame *frame,
                       const TileCounts &tc, uint32_t *err_word, bool no_mip, hipStream_t st) {
-    hipLaunchKernelGGL((k_mark<kFilter, kDesc>), dim3(groups), dim3(kMarkThreads), 0, st, scene->levels,
-                       scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc, err_word, no_mip);
+    if (groups <= 2 * wide_mark_capacity<kFilter, kDesc>())
+        hipLaunchKernelGGL((k_mark<kFilter, kDesc, kMarkThreadsWide>), dim3(groups), dim3(kMarkThreadsWide), 0, st,
+                           scene->levels, scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc,
+                           err_word, no_mip);
+    else
+        hipLaunchKernelGGL((k_mark<kFilter, kDesc, kMarkThreads>), dim3(groups), dim3(kMarkThreads), 0, st,
+                           scene->levels, scene->textures, scene->n_textures, scene->n_levels, tab, frame->vis, tc,
+                           err_word, no_mip);
 }
 
 template <uint32_t kFilter>
