@@ -116,6 +116,84 @@ def test_build_tables_cover_the_short_codes():
             assert int(((fast & 31) > 0).sum() + ((fast & (1 << 15)) > 0).sum()) == want
 
 
+# ------------------------------------------------------- marker layout
+def _segments(data):
+    """(marker, whole segment bytes) of the header up to and including SOS,
+    and the entropy-coded rest (split by segment lengths, not by the
+    library's or the oracle's parser)."""
+    assert data[:2] == b"\xff\xd8"
+    segs, p = [], 2
+    while True:
+        assert data[p] == 0xFF
+        m = data[p + 1]
+        n = (data[p + 2] << 8) | data[p + 3]
+        segs.append((m, data[p:p + 2 + n]))
+        p += 2 + n
+        if m == 0xDA:
+            return segs, data[p:]
+
+
+def _assemble(segs, rest):
+    return b"\xff\xd8" + b"".join(seg for _, seg in segs) + rest
+
+
+def _merged(segs, marker):
+    """The segments of one kind (DQT or DHT) merged into one, where the first was."""
+    body = b"".join(seg[4:] for m, seg in segs if m == marker)
+    one = bytes([0xFF, marker, (len(body) + 2) >> 8, (len(body) + 2) & 255]) + body
+    out, done = [], False
+    for m, seg in segs:
+        if m != marker:
+            out.append((m, seg))
+        elif not done:
+            out.append((m, one))
+            done = True
+    return out
+
+
+def _layouts(data):
+    segs, rest = _segments(data)
+    app = lambda n, payload: (0xE0 + n, bytes([0xFF, 0xE0 + n, 0, len(payload) + 2]) + payload)
+    com = (0xFE, b"\xff\xfe\x00\x08layout")
+    yield "app and comment segments", [app(1, b"Exif\x00\x00"), com] + segs[:-1] + [app(15, b"x" * 9)] + segs[-1:]
+    yield "fill bytes before markers", [(m, b"\xff\xff" + seg) for m, seg in segs]
+    yield "one DQT segment", _merged(segs, 0xDB)
+    # the same with its tables in the other order (each names its slot)
+    merged = _merged(segs, 0xDB)
+    m, one = next(x for x in merged if x[0] == 0xDB)
+    flipped = one[:4] + one[4 + 65:] + one[4:4 + 65]
+    yield "one DQT segment, tables reversed", [(mm, flipped if mm == 0xDB else ss) for mm, ss in merged]
+    yield "one DHT segment", _merged(segs, 0xC4)
+    sof = [x for x in segs if x[0] == 0xC0]
+    tables = [x for x in segs if x[0] in (0xDB, 0xC4)]
+    others = [x for x in segs if x[0] not in (0xC0, 0xDB, 0xC4, 0xDA)]
+    yield "tables between SOF and SOS", others + sof + tables + segs[-1:]
+
+
+@pytest.mark.parametrize("src", ["synth 420", "synth 444", "pil optimised 420"])
+def test_index_is_invariant_to_marker_layout(src):
+    """Re-laid-out markers (APPn and COM segments, fill bytes, tables merged
+    into one segment or moved between SOF and SOS: all legal T.81 layouts)
+    leave the index byte-identical to the canonical file's: the library's
+    marker handling pinned without the oracle's parser."""
+    rgb = synth.texture(91, 72, 56)
+    if src.startswith("synth"):
+        data = synth.encode(rgb, 80, int(src[-3:]))
+    else:
+        b = io.BytesIO()
+        Image.fromarray(rgb).save(b, format="JPEG", quality=80, subsampling=2, optimize=True)
+        data = b.getvalue()
+    ref = jpt.build_index(data)
+    segs, rest = _segments(data)
+    assert _assemble(segs, rest) == data
+    for name, layout in _layouts(data):
+        li = jpt.build_index(_assemble(layout, rest))
+        # every field: sizes, quantisers, Huffman specifications, overheads
+        assert bytes(li.info) == bytes(ref.info), name
+        assert np.array_equal(li.stream, ref.stream) and np.array_equal(li.records, ref.records), name
+        assert np.array_equal(jpt.build_tables(li.info), jpt.build_tables(ref.info)), name
+
+
 # ------------------------------------------------------------ error paths
 def test_errors():
     data = synth.encode(synth.texture(1, 64, 64), 75, 420)
