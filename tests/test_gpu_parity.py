@@ -438,3 +438,23 @@ def test_hash_map_cache(gpu):
         assert maxd <= 1 and tie <= 1.0
         ref, bad = osc.resolve(g, wl0.filter, parity.levels_from_tiles(osc, V, tiles))
         assert np.array_equal(r.views.frame_host(), ref)
+
+
+@pytest.mark.parametrize("filt", [configs.FILTER_NEAREST, configs.FILTER_BILINEAR, configs.FILTER_TRILINEAR])
+def test_resolve_beyond_4_gib_of_texels(gpu, filt):
+    """A cache of more than 2^22 slots (over 4 GiB of texels) takes resolve's
+    64-bit texel addressing; its frame equals the 32-bit path's bit for bit
+    (the frame's blocks sit in the first slots either way)."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    wl = configs.reduced(seed=14, filt=filt)
+    frames = []
+    for n_slots in (None, (1 << 22) + 1):
+        r = jpt.Renderer(wl.textures, wl.views, wl.filter, n_slots=n_slots)
+        r.render()
+        torch.cuda.synchronize()
+        assert r.frame.counters_host()[jpt.CTR_ERROR] == 0
+        frames.append(r.views.frame_host().copy())
+        del r
+        torch.cuda.empty_cache()
+    assert np.array_equal(frames[0], frames[1])
