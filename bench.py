@@ -42,7 +42,7 @@ TRAFFIC = {
     # fused decode, 1080p frame)
     "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "6ea4512cf277df21",
                 "fetch_kib": 447.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
-    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "c4812caac7973002",
+    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "92f7c8d86309e460",
                 "fetch_kib": 21393.2, "write_kib": 8100.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 

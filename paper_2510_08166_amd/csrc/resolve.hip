@@ -4,11 +4,15 @@
 // is needed (the footprint marking makes the result exact); the paper's
 // variant clamped to one MCU is the filter JPT_FILTER_BILINEAR_CLAMPED.
 //
-// A workgroup shades 64 x 16 pixel tiles, 4 rows per lane, walking the
-// tiles of every view in the launch's table with a stride of gridDim.x.  The scene's
-// sampling descriptors are cached in LDS, and for each lane all tap slot
-// lookups are issued before any texel load, and all texel loads before any
-// blend, so that a lane keeps up to 32 independent loads in flight.
+// A workgroup shades 64 x 16 pixel tiles, 4 rows per lane (the rows'
+// G-buffer loads all in flight at once), walking the tiles of every view in
+// the launch's table with a stride of gridDim.x.  The scene's sampling
+// descriptors are cached in LDS.  Per pixel, all slot lookups are issued
+// before any texel load and all texel loads before the blend; the texture
+// addresser spends about the same time on every vector memory instruction
+// whatever its lanes, so a bilinear row's two neighbouring texels come in
+// one 8-byte load, and caches within 4 GiB of texels are addressed with
+// 32-bit offsets from a scalar base.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
