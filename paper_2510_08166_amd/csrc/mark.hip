@@ -166,10 +166,11 @@ __device__ __forceinline__ void set_insert(uint32_t *s_key, uint32_t *s_bits, ui
 // (106 scalar registers allowed 7): 78 scalar registers, the rest spilled to
 // vector lanes; for the 8-wave form that is 4 workgroups per compute unit
 // instead of 3 (1080p: 14.3 against 16.5 us; 16 views with 4 waves: 208
-// against 240 us).  Not the trilinear form, whose vector registers would
-// then spill to memory.
+// against 240 us).  The trilinear form holds two levels' footprints: it asks
+// for 6 waves per SIMD (77 vector registers instead of 85, which allowed 5;
+// the heavy 4K sequence: 78 against 87 us), since 7 or 8 would spill to memory.
 template <uint32_t kFilter, int kDesc, int kThreads>
-__global__ __launch_bounds__(kThreads, kFilter != JPT_FILTER_TRILINEAR ? 8 : 1) void k_mark(const jpt_level_desc *__restrict__ levels,
+__global__ __launch_bounds__(kThreads, kFilter != JPT_FILTER_TRILINEAR ? 8 : 6) void k_mark(const jpt_level_desc *__restrict__ levels,
                                                        const jpt_texture_desc *__restrict__ texs, uint32_t n_tex,
                                                        uint32_t n_lev, const ViewTable tab,
                                                        uint32_t *__restrict__ vis, const TileCounts tc,
