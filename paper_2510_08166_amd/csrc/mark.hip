@@ -400,6 +400,10 @@ __device__ __forceinline__ void tile_total(uint64_t s, uint64_t *__restrict__ ti
     }
 }
 
+// Work items (and blocks) of a scan tile that the counted compaction stages
+// in LDS before storing them as whole rows.
+constexpr uint32_t kEmitStage = 4096;
+
 struct WordCounts {
     uint32_t newm[kWpt];
     uint32_t sub[kWpt];  // work items per block of that word's level
@@ -540,6 +544,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restr
                                                                uint32_t n_slots, uint32_t *__restrict__ counters) {
     __shared__ uint64_t s_red[kScanThreads / 64], s_tot[kScanThreads / 64], s_wave[kScanThreads / 64];
     __shared__ uint32_t s_last;
+    __shared__ uint32_t s_items[kEmitStage], s_blocks[kEmitStage];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tile = blockIdx.x;
     const uint32_t w0 = tile * JPT_SCAN_TILE_WORDS + threadIdx.x * kWpt;
     // offset of the tile (the groups before its group, the tiles before it
@@ -575,20 +580,56 @@ __global__ __launch_bounds__(kScanThreads) void k_emit_counted(uint32_t *__restr
         all += s_tot[k];
     }
     uint32_t item = (uint32_t)base, blk = (uint32_t)(base >> 32);
+    // the tile's first item and block and its counts (uniform)
+    uint64_t off = 0, tot_wg = 0;
+    for (int k = 0; k < kScanThreads / 64; k++) {
+        off += s_red[k];
+        tot_wg += s_wave[k];
+    }
+    const uint32_t item0 = (uint32_t)off, blk0 = (uint32_t)(off >> 32);
+    const uint32_t n_items_wg = (uint32_t)tot_wg, n_blocks_wg = (uint32_t)(tot_wg >> 32);
+    if (n_items_wg <= kEmitStage && n_blocks_wg <= kEmitStage) {
+        // each thread's items and blocks into LDS at their offsets in the
+        // tile, then whole-workgroup stores (bit 31 of a block: its items do
+        // not all fit the work list)
 #pragma unroll
-    for (int i = 0; i < kWpt; i++) {
-        uint32_t m = wc.newm[i];
-        const uint32_t sub = wc.sub[i];
-        while (m) {
-            const uint32_t bit = __builtin_ctz(m);
-            m &= m - 1;
-            const uint32_t b = (w0 + i) * 32 + bit;
-            const bool fits = item + sub <= max_items;
-            for (uint32_t q = 0; q < sub; q++)
-                if (item + q < max_items) work[item + q] = (b << 2) | q;
-            if (slot_of) slot_of[b] = blk < n_slots && fits ? blk : JPT_SLOT_NONE;
-            item += sub;
-            blk += 1;
+        for (int i = 0; i < kWpt; i++) {
+            uint32_t m = wc.newm[i];
+            const uint32_t sub = wc.sub[i];
+            while (m) {
+                const uint32_t bit = __builtin_ctz(m);
+                m &= m - 1;
+                const uint32_t b = (w0 + i) * 32 + bit;
+                for (uint32_t q = 0; q < sub; q++) s_items[item - item0 + q] = (b << 2) | q;
+                s_blocks[blk - blk0] = b | (item + sub <= max_items ? 0u : 0x80000000u);
+                item += sub;
+                blk += 1;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n_items_wg; i += kScanThreads)
+            if (item0 + i < max_items) work[item0 + i] = s_items[i];
+        if (slot_of)
+            for (uint32_t j = threadIdx.x; j < n_blocks_wg; j += kScanThreads) {
+                const uint32_t e = s_blocks[j], s = blk0 + j;
+                slot_of[e & 0x7FFFFFFFu] = s < n_slots && !(e >> 31) ? s : JPT_SLOT_NONE;
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kWpt; i++) {
+            uint32_t m = wc.newm[i];
+            const uint32_t sub = wc.sub[i];
+            while (m) {
+                const uint32_t bit = __builtin_ctz(m);
+                m &= m - 1;
+                const uint32_t b = (w0 + i) * 32 + bit;
+                const bool fits = item + sub <= max_items;
+                for (uint32_t q = 0; q < sub; q++)
+                    if (item + q < max_items) work[item + q] = (b << 2) | q;
+                if (slot_of) slot_of[b] = blk < n_slots && fits ? blk : JPT_SLOT_NONE;
+                item += sub;
+                blk += 1;
+            }
         }
     }
     __syncthreads();
