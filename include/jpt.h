@@ -352,6 +352,13 @@ typedef struct jpt_tuning {       /* launch knobs; NULL = defaults.  Results nev
  * own L2) a contiguous run of pixel tiles in mark and resolve, instead of
  * interleaving neighbouring tiles over all of them. */
 #define JPT_TUNE_XCD_TILES 1u
+/* jpt_tuning.flags: how the bilinear resolves look up a pixel's slots.  By
+ * default a launch of more than one round of workgroups (more pixel tiles
+ * than the GPU holds at once) reads each texel row's two slot-table entries
+ * in one 8-byte load, and a launch of one round reads the four entries one
+ * by one; these flags force one form (both set: JPT_E_ARG). */
+#define JPT_TUNE_RESOLVE_PAIRED 2u
+#define JPT_TUNE_RESOLVE_SINGLE 4u
 
 /* Buffer sizes for rendering a scene's views under `filter` (host query,
  * no device access): what jpt_frame and jpt_cache need so that no frame of

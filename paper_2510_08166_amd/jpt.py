@@ -30,7 +30,7 @@ INDEX_SPLICED, INDEX_PREDICTORS = 0, 1
 SCENE_PREDICTOR_INDEX = 1
 IDCT_MFMA_F16, IDCT_SCALAR_F32, IDCT_FUSED_F32, IDCT_MFMA_BF16 = 0, 1, 2, 3
 FRAME_AUTO = 0xFFFFFFFF
-TUNE_XCD_TILES = 1
+TUNE_XCD_TILES, TUNE_RESOLVE_PAIRED, TUNE_RESOLVE_SINGLE = 1, 2, 4
 CTR_ITEMS, CTR_NEW, CTR_VISIBLE, CTR_ERROR, CTR_ERROR_ITEM, CTR_EVICTED, CTR_RESIDENT, CTR_GRAD_MAX = range(8)
 N_COUNTERS = 16
 ERR_CORRUPT, ERR_CAPACITY, ERR_PIXEL, ERR_INTERNAL, ERR_GRAD = 1, 2, 4, 8, 16

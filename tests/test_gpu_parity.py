@@ -458,3 +458,58 @@ def test_resolve_beyond_4_gib_of_texels(gpu, filt):
         del r
         torch.cuda.empty_cache()
     assert np.array_equal(frames[0], frames[1])
+
+
+@pytest.mark.parametrize("form", ["paired", "single"])
+@pytest.mark.parametrize("filt", [configs.FILTER_BILINEAR, configs.FILTER_BILINEAR_CLAMPED])
+def test_taps_in_the_last_block_id(gpu, filt, form):
+    """Bilinear taps in the scene's last block id and across both wraps of a
+    level, with each form of resolve's slot lookups.  The paired form reads
+    the slot table in 8-byte pairs (a tap's block and the next id); a pair
+    that would start at the last id starts one earlier, and a tap the pair
+    does not hold (a wrap) is read on its own.  The last texture is 128 x 64
+    with one level: 32 blocks, so its bottom-right block is the scene's last
+    id."""
+    from paper_2510_08166_amd import jpt
+    from paper_2510_08166_amd.synth import GPIXEL_DTYPE, make_textures, seed_ints
+    s0, s1 = seed_ints(91, 2)
+    tex = make_textures([(s0, 64, 64, 70, 420, 3), (s1, 128, 64, 80, 420, 1)])
+    H, W = 56, 96
+    y, x = np.mgrid[0:H, 0:W]
+    g = np.zeros((H, W), GPIXEL_DTYPE)
+    # steps of 1.35 texels from near the level's origin past its right edge
+    # (u > 1 wraps) and down to its last texel row (whose y1 wraps to row 0)
+    g["u"] = ((x * 1.35 + 0.4) / 128).astype(np.float32)
+    g["v"] = (((y - 8) * 1.35 + 0.4) / 64).astype(np.float32)
+    g["tex"] = 1
+    g["lod"] = 0.0
+    g["tex"][:8] = 0           # a band of the other texture, between its levels
+    g["v"][:8] = ((y[:8] + 0.5) / 16).astype(np.float32)
+    g["lod"][:8] = 1.3
+    wl = configs.Workload("last block id", tex, [g], filt)
+    t = jpt.TuningC()
+    t.flags = jpt.TUNE_RESOLVE_PAIRED if form == "paired" else jpt.TUNE_RESOLVE_SINGLE
+    r, _, _ = full_parity(wl, tuning=t)
+    assert r.host.n_blocks % 32 == 0
+    assert int(r.cache.slot_of[r.host.n_blocks - 1]) != -1   # the last id was read
+
+
+@pytest.mark.parametrize("filt", [configs.FILTER_BILINEAR, configs.FILTER_BILINEAR_CLAMPED])
+def test_resolve_slot_lookup_forms_agree(gpu, filt):
+    """The paired and the single slot lookups of the bilinear resolves give
+    the same frame bit for bit, on a scene of many textures, levels and
+    block boundaries (the default picks by the launch's rounds of
+    workgroups)."""
+    import torch
+    from paper_2510_08166_amd import jpt
+    wl = configs.quad_scene(5, 12, 512, 40, 95, 6, 640, 360, 40, filt=filt, name="many tiles")
+    frames = []
+    for flags in (jpt.TUNE_RESOLVE_PAIRED, jpt.TUNE_RESOLVE_SINGLE, 0):
+        t = jpt.TuningC()
+        t.flags = flags
+        r = jpt.Renderer(wl.textures, wl.views, wl.filter, tuning=t)
+        r.render()
+        torch.cuda.synchronize()
+        assert r.frame.counters_host()[jpt.CTR_ERROR] == 0
+        frames.append(r.views.frame_host().copy())
+    assert np.array_equal(frames[0], frames[1]) and np.array_equal(frames[0], frames[2])
