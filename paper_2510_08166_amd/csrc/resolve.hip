@@ -176,10 +176,17 @@ __device__ __forceinline__ void fetch_linear(const uint32_t *__restrict__ slot_o
         const bool end = (o0 & 0x3Cu) == 0x3Cu;                   // x0 & 15 == 15
         const bool next = T.blk[t1] == T.blk[t0] && o1 == o0 + 4u;  // x1 = x0 + 1 in the same block row
         const TexelPair pr = load_pair<kNarrow>(texels, min(slot[t0], last_slot), end ? o0 - 4u : o0);
-        uint32_t lone = 0;
-        if (!next) lone = load_texel<kNarrow>(texels, min(slot[t1], last_slot), o1);
-        tex[t0] = end ? pr.y : pr.x;
-        tex[t1] = next ? pr.y : lone;
+        if constexpr (kPairSlots) {
+            // the lone load into a register of its own, and the pair read
+            // only after it is issued: no wait before its branch
+            uint32_t lone = 0;
+            if (!next) lone = load_texel<kNarrow>(texels, min(slot[t1], last_slot), o1);
+            tex[t0] = end ? pr.y : pr.x;
+            tex[t1] = next ? pr.y : lone;
+        } else {  // (one round of workgroups: fewer vector instructions on the chain, measured faster)
+            tex[t0] = end ? pr.y : pr.x;
+            tex[t1] = next ? pr.y : load_texel<kNarrow>(texels, min(slot[t1], last_slot), o1);
+        }
     }
 }
 
@@ -228,7 +235,8 @@ __global__ __launch_bounds__(kThreads) void k_resolve(const jpt_level_desc *__re
             // below 2^29, so their byte offsets fit 32 bits; a block in no slot
             // reads the last slot, a valid address, and matters only if its
             // weight is not 0).  A scene without textures has no blocks: its
-            // pixels read nothing.
+            // pixels read nothing.  (Set on every path: the texel registers
+            // of the paired form stay apart from those of its lone loads.)
             uint32_t slot[kTaps], tex[kTaps];
             if (n_tex == 0) {
 #pragma unroll
