@@ -38,12 +38,12 @@ FRAME1080 = "1080p: 32 x 2048^2 q50-90 4:2:0 8 levels, 200 quads, bilinear"  # c
 # kernel source it was measured on (sha256 prefix of the file); otherwise the
 # bench reports traffic as null.
 TRAFFIC = {
-    # profiles/frame1080_hbm_traffic.txt (k_entropy<true, true, false> and k_resolve<1u, 2, true>,
+    # profiles/frame1080_hbm_traffic.txt (k_entropy<true, true, false> and k_resolve<1u, 2, true, false>,
     # fused decode, 1080p frame)
     "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "6ea4512cf277df21",
                 "fetch_kib": 447.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
-    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "92f7c8d86309e460",
-                "fetch_kib": 21393.2, "write_kib": 8100.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "03587f399b435d4e",
+                "fetch_kib": 21394.4, "write_kib": 8100.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
