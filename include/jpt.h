@@ -469,7 +469,8 @@ jpt_status jpt_idct_color(const jpt_scene *scene, jpt_frame *frame, jpt_cache *c
  * (integer weights: bilinear (sum t*w + 32768) >> 16 per channel,
  * trilinear (a*(256-t) + b*t + 128) >> 8).  Background pixels get 0;
  * invalid pixels and taps in blocks without a slot get JPT_TEXEL_INVALID.
- * Errors: JPT_E_ARG (also a cache of 0 slots), JPT_E_HIP. */
+ * Errors: JPT_E_ARG (also a cache of 0 slots, or a scene of fewer than 32
+ * block ids, which jpt_layout never makes), JPT_E_HIP. */
 jpt_status jpt_resolve(const jpt_scene *scene, const jpt_view *views, uint32_t n_views, uint32_t filter,
                        const jpt_frame *frame, const jpt_cache *cache, const jpt_tuning *tuning, void *stream);
 

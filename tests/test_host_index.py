@@ -251,11 +251,12 @@ def test_device_calls_reject_bad_arguments_without_gpu():
     assert L.jpt_resolve(ctypes.byref(sc), None, 0, 0, None, None, None, None) == jpt.JPT_E_ARG
     assert L.jpt_mark_blocks_static(None, None, 0, 0, None, None, None, None) == jpt.JPT_E_ARG
     assert L.jpt_mark_blocks_static(ctypes.byref(sc), None, 0, 7, ctypes.byref(fr), None, None, None) == jpt.JPT_E_ARG
-    # a scene with textures and fewer than 32 block ids (jpt_layout never
-    # makes one; resolve reads the slot table in pairs that need two ids)
+    # a scene of fewer than 32 block ids, with or without textures (jpt_layout
+    # never makes one; resolve reads the slot table in pairs, and at block 0
+    # for the pixels of a scene without textures)
     fake = 0x1000  # never dereferenced: the checks fail first
-    for n_blocks in (0, 31):
-        sc2 = jpt.SceneC(fake, fake, fake, fake, fake, 1, 1, 1, 1, n_blocks, 0)
+    for n_tex, n_blocks in ((1, 0), (1, 31), (0, 0)):
+        sc2 = jpt.SceneC(fake, fake, fake, fake, fake, 1, n_tex, 1, 1, n_blocks, 0)
         ca = jpt.CacheC(fake, fake, None, None, None, None, None, None, 1, 0, None, 0, 0)
         assert L.jpt_resolve(ctypes.byref(sc2), None, 0, 1, None, ctypes.byref(ca), None, None) == jpt.JPT_E_ARG
     # both forms of the slot lookups forced at once
