@@ -42,8 +42,8 @@ TRAFFIC = {
     # fused decode, 1080p frame)
     "entropy": {"file": "paper_2510_08166_amd/csrc/decode.hip", "sha": "6ea4512cf277df21",
                 "fetch_kib": 447.7, "write_kib": 4290.0, "fetch_scale": 2.0, "write_scale": 1.0},
-    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "03587f399b435d4e",
-                "fetch_kib": 21394.4, "write_kib": 8100.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "resolve": {"file": "paper_2510_08166_amd/csrc/resolve.hip", "sha": "6b6e10c0c7960d85",
+                "fetch_kib": 21393.0, "write_kib": 8100.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
