@@ -2,7 +2,8 @@
 
 The knobs only change how work is spread over the GPU (workgroup counts of
 the persistent decode kernels, tile strides of mark and resolve, the
-XCD-contiguous tile order), never what is computed.  The tuner checks that:
+XCD-contiguous tile order, the form of resolve's slot lookups), never what
+is computed.  The tuner checks that:
 every candidate frame must reproduce the default frame's work list,
 counters, decoded texels and framebuffers byte for byte, or it is rejected.
 
@@ -22,7 +23,8 @@ import numpy as np
 from . import jpt
 
 CANDIDATES = {
-    "flags": [0, jpt.TUNE_XCD_TILES],
+    "flags": [0, jpt.TUNE_XCD_TILES, jpt.TUNE_RESOLVE_PAIRED, jpt.TUNE_RESOLVE_SINGLE,
+              jpt.TUNE_XCD_TILES | jpt.TUNE_RESOLVE_PAIRED, jpt.TUNE_XCD_TILES | jpt.TUNE_RESOLVE_SINGLE],
     "mark_groups": [0, 512, 1024, 2048, 4096],
     "resolve_groups": [0, 512, 1024, 2048, 4096],
     "decode_groups": [0, 256, 512, 1024],

@@ -21,3 +21,12 @@ def test_cache_path_env(monkeypatch, tmp_path):
     assert tune.default_cache_path() == str(tmp_path / "x.json")
     monkeypatch.setenv("JPT_TUNE_CACHE", str(tmp_path))
     assert tune.default_cache_path() == str(tmp_path / "tune.json")
+
+
+def test_flag_candidates_are_valid_launches():
+    """No candidate forces both forms of resolve's slot lookups (jpt_resolve
+    rejects that), and every flag the tuner tries is a declared one."""
+    known = jpt.TUNE_XCD_TILES | jpt.TUNE_RESOLVE_PAIRED | jpt.TUNE_RESOLVE_SINGLE
+    for f in tune.CANDIDATES["flags"]:
+        assert f & ~known == 0
+        assert not (f & jpt.TUNE_RESOLVE_PAIRED and f & jpt.TUNE_RESOLVE_SINGLE)
